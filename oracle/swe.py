@@ -1,0 +1,462 @@
+"""FP64 nodal DG solver for the 2D shallow water equations (oracle).
+
+Test infrastructure only (see the package header).  Every function follows a
+passage of the paper; the nodal-collocation reading (volume term Dr/Ds on the
+nodal fluxes, surface term LIFT on face-node fluxes) is used throughout.
+
+Right-hand side (Section 2, Eq. 2.1-2.3; Section 3, Eq. 3.2-3.3), in strong
+form with the numerical flux of Section 5.1:
+
+    R(Q) = -(d/dx F + d/dy G) + S + LIFT [ Fscale (F(Q-).n - F*.n) ]
+
+* velocities u = hu/h, v = hv/h where h > h0, zero elsewhere;
+* S is the bathymetry source -g h grad B written as
+  -g eta grad B + (g/2) grad(B^2) with eta = h + B (the splitting of the
+  Xing & Shu paper the well-balanced flux is taken from), which keeps the
+  lake at rest exactly steady under collocation;
+* hydrostatic reconstruction h*^{+-} = max(0, h^{+-} + B^{+-} - max(B+, B-))
+  and Q* = (h*, h* u, h* v) (Eq. 5.1);
+* F* = F_LF(Q*+, Q*-) + (0, g/2 (h-)^2 - g/2 (h*-)^2, 0), likewise G*
+  (Eq. 5.2), F_LF the local Lax-Friedrichs flux with the wave speed
+  max |u.n| + sqrt(g h*) taken over both sides of all nodes of the face;
+* reflective walls use the mirror state (h, m - 2 (m.n) n) with B+ = B-.
+
+Limiters after every update (Algorithm 5.1): Q <- TVB(PP(Q)).
+
+* PP (Algorithm 5.2): keep the element when min_j h_j > eps; otherwise
+  project onto P1; when the mean depth is below h0 the element is dry
+  (h = max(mean, 0), hu = hv = 0), else scale the P1 part about the mean by
+  theta = min(1, (hbar - h0) / (hbar - min vertex h1)).
+* TVB (Section 5.3): Cockburn-Shu characteristic TVB limiter on the P1 part
+  with edge-midpoint deviations, then the positivity modification of Eq. 5.3
+  on the depth increments; skipped on dry elements and their face
+  neighbours; an element none of whose characteristic components was
+  limited keeps its full degree-N solution.
+
+Time stepping: Adams-Bashforth 3 (Algorithm 4.1 with one level), started by
+forward Euler and AB2; multi-rate AB3 over levels that step with
+2^{l-1} dt_min (Section 4, Algorithms 4.1 and 5.1) on a tick schedule, the
+coarser neighbours of an active level supplying their AB3 interpolant at
+the half step.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+from .mesh import Mesh, assign_levels, build_mesh, time_step, tvb_stencil, wave_speed
+from .refelem import reference_element
+
+AB_COEFFS = {1: (1.0,), 2: (1.5, -0.5), 3: (23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0)}
+# integral of the Adams-Bashforth interpolant over the first half step, in
+# units of the full step: FE, AB2, AB3
+HALF_COEFFS = {1: (0.5,), 2: (5.0 / 8.0, -1.0 / 8.0), 3: (17.0 / 24.0, -7.0 / 24.0, 2.0 / 24.0)}
+
+PP_KEEP, PP_SCALED, PP_DRY = 0, 1, 2
+TVB_SKIPPED, TVB_KEPT, TVB_LIMITED, TVB_POSITIVE = 0, 1, 2, 3
+
+
+@dataclass
+class Params:
+    g: float = 9.81
+    cfl: float = 0.5
+    h0: float = 1e-5          # dry threshold
+    eps: float = 1e-5         # positivity-limiter trigger
+    tvb_M: float = 10.0
+    tvb_nu: float = 1.5
+    pp: bool = True
+    tvb: bool = True
+    dry_literal: bool = False  # literal dry branch h = h0 instead of max(hbar, 0)
+    max_levels: int = 1
+
+
+@dataclass
+class StepFlags:
+    pp: np.ndarray
+    tvb: np.ndarray
+    neg_mean: int = 0
+
+
+class Solver:
+    """FP64 DG-SWE solver on one triangulation."""
+
+    def __init__(self, vx, vy, etov, N: int, params: Optional[Params] = None,
+                 ghost: Optional[Callable] = None):
+        self.p = params or Params()
+        self.N = N
+        self.ref = reference_element(N)
+        self.mesh: Mesh = build_mesh(vx, vy, etov, self.ref)
+        self.levels = assign_levels(self.mesh, self.p.max_levels)
+        self.stencil = tvb_stencil(self.mesh)
+        self.ghost = ghost
+        self.t = 0.0
+        self.q = None
+        self.B = None
+        self.dt_min = None
+        self.flags = None
+        self.history = []
+        self.flag_counts = []
+
+    # ------------------------------------------------------------------ data
+    @property
+    def K(self):
+        return self.mesh.K
+
+    def nodes(self):
+        return self.mesh.x, self.mesh.y
+
+    def interpolate(self, fn):
+        """Nodal interpolation (the projection Pi_H of the initial data, read as
+        interpolation at the nodes)."""
+        return np.asarray(fn(self.mesh.x, self.mesh.y), dtype=np.float64)
+
+    def set_state(self, h, hu, hv, B, limit: bool = True):
+        """Q^0 = TVB(PP(Pi_H Q^0)) (first line of Algorithm 5.1); the time step
+        uses the wave speed of the interpolated initial data."""
+        self.B = np.array(B, dtype=np.float64)
+        q = np.stack([np.asarray(h, np.float64), np.asarray(hu, np.float64),
+                      np.asarray(hv, np.float64)]).copy()
+        a_max = wave_speed(q[0], q[1], q[2], self.p.g, self.p.h0)
+        self.dt_min = time_step(self.mesh, self.N, self.p.cfl, a_max)
+        if limit:
+            q, self.flags = self.limit(q)
+        self.q = q
+        self.t = 0.0
+        self.history = []
+        self.flag_counts = []
+        self._mr = None
+
+    # ------------------------------------------------------------------ RHS
+    def ddr(self, f):
+        return f @ self.ref.Dr.T
+
+    def dds(self, f):
+        return f @ self.ref.Ds.T
+
+    def ddx(self, f):
+        m = self.mesh
+        return m.rx[:, None] * self.ddr(f) + m.sx[:, None] * self.dds(f)
+
+    def ddy(self, f):
+        m = self.mesh
+        return m.ry[:, None] * self.ddr(f) + m.sy[:, None] * self.dds(f)
+
+    def velocity(self, h, hu, hv):
+        wet = h > self.p.h0
+        hs = np.where(wet, h, 1.0)
+        return np.where(wet, hu / hs, 0.0), np.where(wet, hv / hs, 0.0)
+
+    def traces(self, q, B, t, qP_override=None):
+        """Interior (-) and exterior (+) traces at the 3*Nfp face nodes."""
+        ref, m = self.ref, self.mesh
+        fm = ref.fmask.reshape(-1)
+        qM = q[:, :, fm]
+        BM = B[:, fm]
+        src = q if qP_override is None else qP_override
+        qP = src.reshape(3, -1)[:, m.vmapP]
+        BP = B.reshape(-1)[m.vmapP]
+        Nfp = ref.Nfp
+        nx = np.repeat(m.nx, Nfp, axis=1)
+        ny = np.repeat(m.ny, Nfp, axis=1)
+        wall = np.repeat(m.wall, Nfp, axis=1)
+        if self.ghost is None:
+            mn = qM[1] * nx + qM[2] * ny
+            ghost = np.stack([qM[0], qM[1] - 2.0 * mn * nx, qM[2] - 2.0 * mn * ny])
+        else:
+            xf = m.x[:, fm]
+            yf = m.y[:, fm]
+            gh, ghu, ghv = self.ghost(xf, yf, t)
+            ghost = np.stack([gh, ghu, ghv])
+        qP = np.where(wall[None], ghost, qP)
+        BP = np.where(wall, BM, BP)
+        return qM, qP, BM, BP, nx, ny
+
+    def rhs(self, q, B, t=0.0, qP_override=None):
+        ref, m, p = self.ref, self.mesh, self.p
+        g = p.g
+        h, hu, hv = q
+        u, v = self.velocity(h, hu, hv)
+        F = np.stack([hu, hu * u + 0.5 * g * h * h, hu * v])
+        G = np.stack([hv, hv * u, hv * v + 0.5 * g * h * h])
+        R = -(self.ddx(F) + self.ddy(G))
+        eta = h + B
+        R[1] += -g * eta * self.ddx(B) + 0.5 * g * self.ddx(B * B)
+        R[2] += -g * eta * self.ddy(B) + 0.5 * g * self.ddy(B * B)
+
+        qM, qP, BM, BP, nx, ny = self.traces(q, B, t, qP_override)
+        hM, huM, hvM = qM
+        hP, huP, hvP = qP
+        uM, vM = self.velocity(hM, huM, hvM)
+        uP, vP = self.velocity(hP, huP, hvP)
+        Bmax = np.maximum(BM, BP)
+        hsM = np.maximum(0.0, hM + BM - Bmax)
+        hsP = np.maximum(0.0, hP + BP - Bmax)
+        unM = uM * nx + vM * ny
+        unP = uP * nx + vP * ny
+        lam = np.maximum(np.abs(unM) + np.sqrt(g * hsM), np.abs(unP) + np.sqrt(g * hsP))
+        Nfp = ref.Nfp
+        lam = np.repeat(lam.reshape(self.K, 3, Nfp).max(axis=2), Nfp, axis=1)
+        qsM = np.stack([hsM, hsM * uM, hsM * vM])
+        qsP = np.stack([hsP, hsP * uP, hsP * vP])
+
+        def flux_n(hs, u, v, un):
+            return np.stack([hs * un,
+                             hs * u * un + 0.5 * g * hs * hs * nx,
+                             hs * v * un + 0.5 * g * hs * hs * ny])
+
+        f_lf = 0.5 * (flux_n(hsM, uM, vM, unM) + flux_n(hsP, uP, vP, unP)) \
+            - 0.5 * lam * (qsP - qsM)
+        corr = 0.5 * g * (hM * hM - hsM * hsM)
+        fstar = f_lf + np.stack([np.zeros_like(corr), corr * nx, corr * ny])
+        fM = np.stack([huM * nx + hvM * ny,
+                       (huM * uM + 0.5 * g * hM * hM) * nx + huM * vM * ny,
+                       hvM * uM * nx + (hvM * vM + 0.5 * g * hM * hM) * ny])
+        fs = np.repeat(m.fscale, Nfp, axis=1)
+        R += (fs * (fM - fstar)) @ ref.LIFT.T
+        return R
+
+    # -------------------------------------------------------------- limiters
+    def means(self, q):
+        return (q @ self.ref.w) / 2.0
+
+    def pp_limit(self, q, active=None):
+        """Positivity-preserving limiter M Pi_H of Algorithm 5.2."""
+        ref, p = self.ref, self.p
+        q = q.copy()
+        K = q.shape[1]
+        code = np.zeros(K, dtype=np.uint8)
+        hmin = q[0].min(axis=1)
+        trig = hmin <= p.eps
+        if active is not None:
+            trig &= active
+        neg = 0
+        if np.any(trig):
+            qt = q[:, trig, :]
+            mt = self.means(qt)
+            q1 = qt @ ref.proj1.T
+            h1min = (qt[0] @ ref.p1_vert.T).min(axis=1)
+            den = mt[0] - h1min
+            theta = np.where(den > 0.0,
+                             np.minimum(1.0, (mt[0] - p.h0) / np.where(den > 0.0, den, 1.0)),
+                             1.0)
+            new = mt[:, :, None] + theta[None, :, None] * (q1 - mt[:, :, None])
+            dry = mt[0] < p.h0
+            neg = int(np.sum(mt[0] < 0.0))
+            hdry = np.full(mt[0].shape, p.h0) if p.dry_literal else np.maximum(mt[0], 0.0)
+            new[0] = np.where(dry[:, None], hdry[:, None], new[0])
+            new[1] = np.where(dry[:, None], 0.0, new[1])
+            new[2] = np.where(dry[:, None], 0.0, new[2])
+            q[:, trig, :] = new
+            code[trig] = np.where(dry, PP_DRY, PP_SCALED)
+        return q, code, neg
+
+    def tvb_limit(self, q, pp_code, active=None, means=None):
+        """Characteristic TVB limiter with the positivity modification (Eq. 5.3).
+
+        ``means`` (3, K) are the neighbour means to use (the post-PP snapshot);
+        ``active`` restricts which elements are limited (multi-rate)."""
+        ref, m, st, p = self.ref, self.mesh, self.stencil, self.p
+        K = m.K
+        g = p.g
+        q = q.copy()
+        if means is None:
+            means = self.means(q)
+        own = self.means(q)
+        dry = pp_code == PP_DRY
+        nb_dry = np.where(m.wall, False, dry[m.etoe]).any(axis=1)
+        work = ~dry & ~nb_dry
+        if active is not None:
+            work &= active
+        code = np.zeros(K, dtype=np.uint8)
+        idx = np.nonzero(work)[0]
+        if idx.size == 0:
+            return q, code
+        qa = q[:, idx, :]
+        qbar = own[:, idx]
+        dev = np.einsum("ij,ckj->cki", ref.p1_mid, qa) - qbar[:, :, None]      # (3, n, 3 edges)
+        nbm = means[:, m.etoe[idx]]                                            # (3, n, 3 faces)
+        nxf, nyf = m.nx[idx], m.ny[idx]
+        mn = qbar[1][:, None] * nxf + qbar[2][:, None] * nyf
+        ghost = np.stack([np.broadcast_to(qbar[0][:, None], mn.shape),
+                          qbar[1][:, None] - 2.0 * mn * nxf,
+                          qbar[2][:, None] - 2.0 * mn * nyf])
+        wall = m.wall[idx]
+        nbm = np.where(wall[None], ghost, nbm)
+        diff = nbm - qbar[:, :, None]                                          # (3, n, 3)
+        hb = qbar[0]
+        ub = qbar[1] / hb
+        vb = qbar[2] / hb
+        c = np.sqrt(g * hb)
+        M2 = p.tvb_M * st.dk[idx] ** 2
+        n = idx.size
+        ar = np.arange(n)
+        delta = np.zeros((3, n, 3))
+        all_a1 = np.ones(n, dtype=bool)
+        for i in range(3):
+            pj = st.pair[idx, i, 0]
+            pk = st.pair[idx, i, 1]
+            dbar = st.alpha[idx, i, 0] * diff[:, ar, pj] + st.alpha[idx, i, 1] * diff[:, ar, pk]
+            ex, ey = st.direction[idx, i, 0], st.direction[idx, i, 1]
+            un = ub * ex + vb * ey
+            ut = -ub * ey + vb * ex
+            L = np.stack([
+                np.stack([(un + c) / (2 * c), -ex / (2 * c), -ey / (2 * c)], axis=-1),
+                np.stack([-ut, -ey, ex], axis=-1),
+                np.stack([-(un - c) / (2 * c), ex / (2 * c), ey / (2 * c)], axis=-1)], axis=1)
+            Rm = np.stack([
+                np.stack([np.ones(n), np.zeros(n), np.ones(n)], axis=-1),
+                np.stack([ub - c * ex, -ey, ub + c * ex], axis=-1),
+                np.stack([vb - c * ey, ex, vb + c * ey], axis=-1)], axis=1)
+            a1 = np.einsum("nab,bn->an", L, dev[:, :, i])
+            a2 = p.tvb_nu * np.einsum("nab,bn->an", L, dbar)
+            small = np.abs(a1) <= M2[None, :]
+            same = np.sign(a1) == np.sign(a2)
+            mm = np.where(same, np.sign(a1) * np.minimum(np.abs(a1), np.abs(a2)), 0.0)
+            mt = np.where(small, a1, mm)
+            ret = small | (a1 == 0.0) | (same & (np.abs(a1) <= np.abs(a2)))
+            all_a1 &= ret.all(axis=0)
+            delta[:, :, i] = np.einsum("nab,bn->an", Rm, mt)
+        code_a = np.full(n, TVB_KEPT, dtype=np.uint8)
+        lim = ~all_a1
+        if np.any(lim):
+            D = delta[:, lim, :]
+            pos = np.maximum(D, 0.0).sum(axis=2)
+            neg = np.maximum(-D, 0.0).sum(axis=2)
+            thp = np.where(pos > 0.0, np.minimum(1.0, neg / np.where(pos > 0.0, pos, 1.0)), 1.0)
+            thm = np.where(neg > 0.0, np.minimum(1.0, pos / np.where(neg > 0.0, neg, 1.0)), 1.0)
+            Dh = thp[:, :, None] * np.maximum(D, 0.0) - thm[:, :, None] * np.maximum(-D, 0.0)
+            # Eq. 5.3 on the depth increments
+            hbl = hb[lim]
+            d = Dh[0]
+            S = d.sum(axis=1)
+            dbar_h = S / 3.0
+            vert = S[:, None] - 2.0 * d                    # -D_i + D_j + D_k
+            vmin = vert.min(axis=1)
+            fix = hbl + vmin < p.h0
+            den = dbar_h - vmin
+            theta = np.where(den > 0.0, (hbl + dbar_h - p.h0) / np.where(den > 0.0, den, 1.0), 0.0)
+            theta = np.clip(theta, 0.0, 1.0)
+            dfix = dbar_h[:, None] + theta[:, None] * (d - dbar_h[:, None])
+            Dh[0] = np.where(fix[:, None], dfix, d)
+            newq = qbar[:, lim, None] + np.einsum("cni,ij->cnj", Dh, ref.phi_mid)
+            qa[:, lim, :] = newq
+            code_a[lim] = np.where(fix, TVB_POSITIVE, TVB_LIMITED)
+        q[:, idx, :] = qa
+        code[idx] = code_a
+        return q, code
+
+    def limit(self, q, active=None):
+        """Lambda Pi_H M Pi_H of Algorithm 5.1 (PP first, then TVB)."""
+        p = self.p
+        K = q.shape[1]
+        pp = np.zeros(K, dtype=np.uint8)
+        neg = 0
+        if p.pp:
+            q, pp, neg = self.pp_limit(q, active)
+        tv = np.zeros(K, dtype=np.uint8)
+        if p.tvb:
+            q, tv = self.tvb_limit(q, pp, active)
+        return q, StepFlags(pp, tv, neg)
+
+    # ------------------------------------------------------------ stepping
+    def step(self):
+        """One single-rate AB3 step followed by the limiters."""
+        R = self.rhs(self.q, self.B, self.t)
+        self.history.insert(0, R)
+        del self.history[3:]
+        coeffs = AB_COEFFS[len(self.history)]
+        incr = sum(c * r for c, r in zip(coeffs, self.history))
+        qt = self.q + self.dt_min * incr
+        self.q, self.flags = self.limit(qt)
+        self.t += self.dt_min
+        self.flag_counts.append((np.bincount(self.flags.pp, minlength=3),
+                                 np.bincount(self.flags.tvb, minlength=4),
+                                 self.flags.neg_mean))
+
+    def run(self, steps: int):
+        if self.p.max_levels > 1:
+            for _ in range(steps):
+                self.mrab_coarse_step()
+        else:
+            for _ in range(steps):
+                self.step()
+        return self.q
+
+    # ----------------------------------------------------------- multi-rate
+    def mrab_coarse_step(self):
+        """One coarse step of multi-rate AB3 (Algorithms 4.1 and 5.1).
+
+        Levels l = 1..L step with dt_l = 2^{l-1} dt_min.  A coarse step has
+        2^{L-1} ticks of dt_min; at tick k the levels with k mod 2^{l-1} == 0
+        are active.  All active levels first evaluate R at the common time
+        (finer neighbours are always active and in step; an inactive coarser
+        neighbour supplies its AB3 interpolant at its half step, written when
+        it last stepped), then they update, coarsest first, then the limiters
+        run on the active elements with the post-PP means of all elements.
+        """
+        L = self.p.max_levels
+        lev = self.levels
+        K = self.K
+        if self._mr is None:
+            self._mr = {"hist": [[] for _ in range(L + 1)],
+                        "half": self.q.copy(), "tick": 0}
+        st = self._mr
+        for k in range(2 ** (L - 1)):
+            active_levels = [l for l in range(1, L + 1) if k % (2 ** (l - 1)) == 0]
+            active = np.isin(lev, active_levels)
+            # exterior state: current state, except inactive elements supply
+            # their half-step interpolant
+            ext = np.where(active[None, :, None], self.q, st["half"])
+            R = self.rhs(self.q, self.B, self.t, qP_override=ext)
+            qt = self.q.copy()
+            half = st["half"]
+            for l in sorted(active_levels, reverse=True):
+                sel = lev == l
+                hist = st["hist"][l]
+                hist.insert(0, R[:, sel, :])
+                del hist[3:]
+                dtl = self.dt_min * 2 ** (l - 1)
+                coeffs = AB_COEFFS[len(hist)]
+                qt[:, sel, :] = self.q[:, sel, :] + dtl * sum(c * r for c, r in zip(coeffs, hist))
+                if l > 1:
+                    hc = HALF_COEFFS[len(hist)]
+                    half[:, sel, :] = self.q[:, sel, :] + dtl * sum(
+                        c * r for c, r in zip(hc, hist))
+            qt, flags = self.limit_multirate(qt, active)
+            self.q = qt
+            self.flags = flags
+            self.t += self.dt_min
+        return self.q
+
+    def limit_multirate(self, q, active):
+        p = self.p
+        K = q.shape[1]
+        pp = np.zeros(K, dtype=np.uint8)
+        neg = 0
+        prev_pp = self.flags.pp if self.flags is not None else np.zeros(K, np.uint8)
+        if p.pp:
+            q, pp_new, neg = self.pp_limit(q, active)
+            pp = np.where(active, pp_new, prev_pp)
+        tv = np.zeros(K, dtype=np.uint8)
+        if p.tvb:
+            q, tv = self.tvb_limit(q, pp, active)
+        return q, StepFlags(pp, tv, neg)
+
+    # --------------------------------------------------------- diagnostics
+    def mass(self, q=None):
+        q = self.q if q is None else q
+        return float(np.sum(self.mesh.J * (q[0] @ self.ref.w)))
+
+    def rel_l2(self, q_test, q_ref=None, fields=(0,)):
+        """sqrt(sum_k J_k e.M e) / sqrt(sum_k J_k q.M q) over the given fields."""
+        q_ref = self.q if q_ref is None else q_ref
+        M = self.ref.M
+        num = 0.0
+        den = 0.0
+        for c in fields:
+            e = q_test[c] - q_ref[c]
+            num += float(np.sum(self.mesh.J * np.einsum("ki,ij,kj->k", e, M, e)))
+            den += float(np.sum(self.mesh.J * np.einsum("ki,ij,kj->k", q_ref[c], M, q_ref[c])))
+        return np.sqrt(num) / np.sqrt(den) if den > 0 else np.sqrt(num)

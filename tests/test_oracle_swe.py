@@ -1,0 +1,341 @@
+"""Pins for the oracle's DG-SWE solver against what the paper and the
+mathematics fix: exact steady states, conservation, consistency with the PDE,
+convergence order, exact Adams-Bashforth coefficients, limiter invariants."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.swe import AB_COEFFS, HALF_COEFFS, PP_DRY, PP_KEEP, PP_SCALED, Params, Solver
+
+
+def make(wl, params=None, inst=0, **kw):
+    ins = wl.instances[inst]
+    p = params or Params(g=wl.g, cfl=wl.cfl, **kw)
+    s = Solver(ins.vx, ins.vy, ins.etov, wl.N, p)
+    x, y = s.nodes()
+    B = s.interpolate(ins.bathymetry)
+    h, hu, hv = ins.initial(x, y)
+    s.set_state(h, hu, hv, B)
+    return s
+
+
+# --------------------------------------------------------------------- RHS
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_lake_at_rest_is_steady(N):
+    """Exact C-property (Section 5.1): still water over a non-constant bed."""
+    s = make(W.lake_at_rest(n=5, N=N))
+    R = s.rhs(s.q, s.B)
+    assert np.max(np.abs(R)) < 1e-12
+    s.run(10)
+    assert np.max(np.abs(s.q[0] + s.B - 1.0)) < 1e-13
+    assert np.max(np.abs(s.q[1:])) < 1e-12
+
+
+def test_lake_at_rest_discontinuous_bed():
+    """With a bed that jumps across faces only the hydrostatic reconstruction
+    and the pressure correction of Eq. 5.1-5.2 keep still water steady."""
+    wl = W.lake_at_rest(n=6, N=3)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 3, Params())
+    x, _ = s.nodes()
+    rng = np.random.default_rng(5)
+    B = np.repeat(rng.uniform(0.0, 0.4, s.K)[:, None], x.shape[1], axis=1) + 0.2 * x
+    q = np.stack([1.0 - B, 0 * B, 0 * B])
+    assert np.max(np.abs(s.rhs(q, B))) < 1e-12
+    # a bed emerging above the still water (dry element next to wet ones)
+    B[3] = 1.5
+    q = np.stack([np.maximum(1.0 - B, 0.0), 0 * B, 0 * B])
+    assert np.max(np.abs(s.rhs(q, B))) < 1e-12
+
+
+def test_uniform_flow_interior_residual_zero():
+    wl = W.lake_at_rest(n=6, N=3)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 3, Params(pp=False, tvb=False))
+    x, y = s.nodes()
+    q = np.stack([np.full_like(x, 1.3), np.full_like(x, 0.4), np.full_like(x, -0.2)])
+    R = s.rhs(q, np.zeros_like(x))
+    inner = ~s.mesh.wall.any(axis=1)
+    assert np.max(np.abs(R[:, inner, :])) < 1e-12
+
+
+def test_rhs_conserves_mass_with_walls():
+    wl = W.small_wetdry(n=6, N=3)
+    s = make(wl)
+    rng = np.random.default_rng(0)
+    q = np.stack([0.5 + rng.uniform(0, 0.5, s.q[0].shape), rng.normal(0, 0.3, s.q[0].shape),
+                  rng.normal(0, 0.3, s.q[0].shape)])
+    R = s.rhs(q, s.B)
+    total = np.sum(s.mesh.J * (R[0] @ s.ref.w))
+    scale = np.sum(s.mesh.J * (np.abs(R[0]) @ s.ref.w))
+    assert abs(total) < 1e-13 * scale
+
+
+def _manufactured(g):
+    def state(x, y):
+        h = 1.0 + 0.2 * np.sin(2 * x + 1) * np.cos(3 * y)
+        hu = 0.3 * np.cos(x - 2 * y)
+        hv = -0.2 * np.sin(x * y + 0.5)
+        return h, hu, hv
+
+    def bed(x, y):
+        return 0.1 * np.cos(x + y) + 0.05 * x
+
+    def pde_rhs(x, y, d=1e-5):
+        def F(x, y):
+            h, hu, hv = state(x, y)
+            u, v = hu / h, hv / h
+            return np.stack([hu, hu * u + 0.5 * g * h * h, hu * v])
+
+        def G(x, y):
+            h, hu, hv = state(x, y)
+            u, v = hu / h, hv / h
+            return np.stack([hv, hv * u, hv * v + 0.5 * g * h * h])
+
+        dFx = (F(x + d, y) - F(x - d, y)) / (2 * d)
+        dGy = (G(x, y + d) - G(x, y - d)) / (2 * d)
+        h = state(x, y)[0]
+        Bx = (bed(x + d, y) - bed(x - d, y)) / (2 * d)
+        By = (bed(x, y + d) - bed(x, y - d)) / (2 * d)
+        S = np.stack([0 * h, -g * h * Bx, -g * h * By])
+        return -(dFx + dGy) + S
+
+    return state, bed, pde_rhs
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_rhs_consistent_with_pde(N):
+    """R(Q_H) approaches -div F + S of the PDE (Eq. 2.2) at order ~N on smooth
+    data; a dropped term or wrong sign anywhere in volume, source or surface
+    terms breaks this."""
+    g = 9.81
+    state, bed, pde_rhs = _manufactured(g)
+    errs = []
+    for n in (8, 16, 32):
+        vx, vy, etov = W.structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0)
+        s = Solver(vx, vy, etov, N, Params(g=g, pp=False, tvb=False))
+        x, y = s.nodes()
+        q = np.stack(state(x, y))
+        B = bed(x, y)
+        R = s.rhs(q, B)
+        exact = pde_rhs(x, y)
+        inner = ~s.mesh.wall.any(axis=1)
+        errs.append(np.max(np.abs(R - exact)[:, inner, :]))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > N - 0.5), (errs, rates)
+
+
+def _vortex_exact(beta=5.0):
+    def exact(x, y, t):
+        xx = x - t
+        r2 = xx ** 2 + y ** 2
+        h = 1 - beta ** 2 / (32 * np.pi ** 2) * np.exp(2 * (1 - r2))
+        u = 1 - beta * np.exp(1 - r2) * y / (2 * np.pi)
+        v = beta * np.exp(1 - r2) * xx / (2 * np.pi)
+        return h, h * u, h * v
+    return exact
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_vortex_convergence_order(N):
+    """Translating vortex of Section 6.2 (g = 2, Dirichlet data = exact
+    solution, limiters off): least-squares EOC of the depth error at least
+    N + 1/2 - 0.2 (Table 6.1)."""
+    exact = _vortex_exact()
+    T = 0.25
+    errs, Hs = [], []
+    for n in (10, 20, 40):
+        vx, vy, etov = W.structured_mesh(int(1.5 * n), int(1.2 * n), -5, 10, -6, 6)
+        s = Solver(vx, vy, etov, N, Params(g=2.0, cfl=0.5, pp=False, tvb=False), ghost=exact)
+        x, y = s.nodes()
+        s.set_state(*exact(x, y, 0.0), 0 * x)
+        nst = int(np.ceil(T / s.dt_min))
+        s.dt_min = T / nst
+        s.run(nst)
+        errs.append(s.rel_l2(np.stack(exact(x, y, T)), fields=(0,)))
+        Hs.append(10.0 / n)
+    eoc = np.polyfit(np.log(Hs), np.log(errs), 1)[0]
+    assert eoc >= N + 0.5 - 0.2, (errs, eoc)
+
+
+# --------------------------------------------------------------- time
+def test_adams_bashforth_coefficients_exact_for_quadratics():
+    """AB3 integrates the quadratic interpolant of the last three RHS values
+    (Algorithm 4.1): exact for y' = c0 + c1 t + c2 t^2; the half-step weights
+    integrate the same interpolant over the first half step."""
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        c = rng.normal(size=3)
+        dt = rng.uniform(0.1, 2.0)
+        t0 = rng.uniform(-1, 1)
+        f = lambda t: c[0] + c[1] * t + c[2] * t * t  # noqa: E731
+        prim = lambda t: c[0] * t + c[1] * t ** 2 / 2 + c[2] * t ** 3 / 3  # noqa: E731
+        fs = [f(t0 - s * dt) for s in range(3)]
+        assert abs(dt * sum(a * b for a, b in zip(AB_COEFFS[3], fs))
+                   - (prim(t0 + dt) - prim(t0))) < 1e-12
+        assert abs(dt * sum(a * b for a, b in zip(HALF_COEFFS[3], fs))
+                   - (prim(t0 + dt / 2) - prim(t0))) < 1e-12
+        g = lambda t: c[0] + c[1] * t  # noqa: E731
+        gp = lambda t: c[0] * t + c[1] * t ** 2 / 2  # noqa: E731
+        gs = [g(t0 - s * dt) for s in range(2)]
+        assert abs(dt * sum(a * b for a, b in zip(AB_COEFFS[2], gs)) - (gp(t0 + dt) - gp(t0))) < 1e-12
+        assert abs(dt * sum(a * b for a, b in zip(HALF_COEFFS[2], gs))
+                   - (gp(t0 + dt / 2) - gp(t0))) < 1e-12
+
+
+def test_solver_step_exact_for_quadratic_forcing():
+    s = make(W.lake_at_rest(n=2, N=1), Params(pp=False, tvb=False))
+    c = np.array([0.3, -1.2, 0.7])
+    f = lambda t: c[0] + c[1] * t + c[2] * t * t  # noqa: E731
+    prim = lambda t: c[0] * t + c[1] * t ** 2 / 2 + c[2] * t ** 3 / 3  # noqa: E731
+    s.rhs = lambda q, B, t=0.0, qP_override=None: np.full_like(q, f(t))
+    dt = s.dt_min = 0.05
+    s.t = 2 * dt
+    s.history = [np.full_like(s.q, f(dt)), np.full_like(s.q, f(0.0))]
+    q0 = s.q.copy()
+    for _ in range(4):
+        s.step()
+    assert np.max(np.abs(s.q - (q0 + prim(s.t) - prim(2 * dt)))) < 1e-12
+
+
+def test_mrab_one_level_is_ab3_bitwise():
+    wl = W.small_wetdry(n=6, N=2)
+    a = make(wl, Params(g=wl.g, cfl=0.2))
+    b = make(wl, Params(g=wl.g, cfl=0.2))
+    for _ in range(15):
+        a.step()
+        b.mrab_coarse_step()
+    assert np.array_equal(a.q, b.q)
+
+
+def test_mrab_two_levels_converges():
+    """Two-level multi-rate AB3 converges to the single-rate solution as
+    dt_min shrinks (order >= 2 including the FE/AB2 start)."""
+    wl = W.c3(n0=2, n_bands=2)
+    ins = wl.instances[0]
+
+    def run(dt, levels, T):
+        s = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=0.3, max_levels=levels,
+                                                      pp=False, tvb=False))
+        x, y = s.nodes()
+        s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry))
+        s.dt_min = dt
+        n = int(round(T / (dt * 2 ** (levels - 1))))
+        s.run(n)
+        assert np.unique(s.levels).size == levels
+        return s.q
+
+    s0 = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=0.3, max_levels=2))
+    x, y = s0.nodes()
+    s0.set_state(*ins.initial(x, y), s0.interpolate(ins.bathymetry))
+    dt0 = s0.dt_min
+    T = 32 * dt0
+    ref = run(dt0 / 16, 1, T)
+    e1 = np.max(np.abs(run(dt0, 2, T) - ref))
+    e2 = np.max(np.abs(run(dt0 / 2, 2, T) - ref))
+    assert e1 / e2 > 3.5, (e1, e2)
+
+
+# --------------------------------------------------------------- limiters
+def _pp_solver():
+    return make(W.small_wetdry(n=6, N=3), Params(cfl=0.2))
+
+
+def test_pp_limiter_invariants():
+    s = _pp_solver()
+    rng = np.random.default_rng(4)
+    K, Np = s.q[0].shape
+    q = np.stack([rng.uniform(-0.05, 0.3, (K, Np)), rng.normal(0, 0.1, (K, Np)),
+                  rng.normal(0, 0.1, (K, Np))])
+    q[0, :10] = rng.uniform(0.2, 0.3, (10, Np))          # some untouched elements
+    q[0, 10:20] = rng.uniform(-0.02, 0.015, (10, Np))    # some dry, some negative means
+    means = s.means(q)
+    out, code, neg = s.pp_limit(q)
+    mo = s.means(out)
+    keep = code == PP_KEEP
+    scaled = code == PP_SCALED
+    dry = code == PP_DRY
+    assert keep.sum() >= 10 and scaled.sum() > 0 and dry.sum() > 0
+    assert np.array_equal(out[:, keep], q[:, keep])
+    assert np.max(np.abs(mo[:, scaled] - means[:, scaled])) < 1e-14
+    assert np.max(np.abs(mo[0, dry] - np.maximum(means[0, dry], 0))) < 1e-14
+    assert np.all(out[1:, dry] == 0.0)
+    assert np.all(out[0] >= 0.0)
+    # theta < 1 puts the lowest vertex exactly on h0
+    vert = out[0] @ s.ref.p1_vert.T
+    tight = scaled & (vert.min(axis=1) < means[0] - 1e-12)
+    h1 = (q[0] @ s.ref.p1_vert.T).min(axis=1)
+    theta_lt1 = tight & (h1 < s.p.h0)
+    assert theta_lt1.sum() > 0
+    assert np.max(np.abs(vert[theta_lt1].min(axis=1) - s.p.h0)) < 1e-14
+    assert np.all(out[0, scaled] >= s.p.h0 - 1e-14)
+    # idempotent
+    out2, _, _ = s.pp_limit(out)
+    assert np.max(np.abs(out2 - out)) < 1e-14
+    assert neg == int(np.sum(means[0][~keep] < 0))
+
+
+def test_tvb_keeps_linear_and_constant_data():
+    wl = W.lake_at_rest(n=8, N=3)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 3, Params(tvb_M=0.0))
+    x, y = s.nodes()
+    q = np.stack([1.0 + 0.3 * x - 0.2 * y, 0.1 + 0.05 * x + 0.02 * y, -0.03 + 0.04 * y])
+    pp = np.zeros(s.K, dtype=np.uint8)
+    out, code = s.tvb_limit(q, pp)
+    st = s.stencil
+    inner = ~s.mesh.wall.any(axis=1) & np.all(st.pair[:, :, 0] != st.pair[:, :, 1], axis=1)
+    assert inner.sum() > 20
+    assert np.max(np.abs(out[:, inner] - q[:, inner])) < 1e-13
+    assert np.all(code[inner] == 1)
+    qc = np.stack([np.full_like(x, 0.7), np.full_like(x, 0.1), np.full_like(x, -0.2)])
+    outc, _ = s.tvb_limit(qc, pp)
+    assert np.max(np.abs(outc - qc)) < 1e-14
+
+
+def test_tvb_limits_discontinuity_preserving_means_and_positivity():
+    wl = W.lake_at_rest(n=8, N=3)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 3, Params(tvb_M=0.0, h0=1e-3))
+    x, y = s.nodes()
+    rng = np.random.default_rng(7)
+    h = np.where(x + 0.3 * y < 0.55, 1.0, 0.002) + 0.001 * rng.uniform(size=x.shape) * x
+    q = np.stack([h, 0.3 * h * np.sin(3 * y), 0.1 * h])
+    pp = np.zeros(s.K, dtype=np.uint8)
+    before = s.means(q)
+    out, code = s.tvb_limit(q, pp)
+    after = s.means(out)
+    assert np.sum(code >= 2) > 0 and np.sum(code == 3) > 0
+    assert np.max(np.abs(after - before)) < 1e-13
+    vert = out[0] @ s.ref.p1_vert.T
+    lim = code >= 2
+    assert np.all(vert[lim].min(axis=1) >= s.p.h0 - 1e-12)
+    # limited elements are linear
+    assert np.max(np.abs(out[:, lim] @ s.ref.proj1.T - out[:, lim])) < 1e-12
+
+
+def test_tvb_skips_dry_and_their_neighbours():
+    s = _pp_solver()
+    q = s.q.copy()
+    pp = s.flags.pp.copy()
+    k = int(np.nonzero(~s.mesh.wall.any(axis=1) & (pp != PP_DRY))[0][0])
+    pp[k] = PP_DRY
+    _, code = s.tvb_limit(q, pp)
+    assert code[k] == 0
+    for k2, wall in zip(s.mesh.etoe[k], s.mesh.wall[k]):
+        if not wall:
+            assert code[k2] == 0
+
+
+# ------------------------------------------------------------ whole solver
+def test_wetdry_run_conserves_mass_and_positivity():
+    s = make(W.small_wetdry(n=10, N=3), Params(cfl=0.2))
+    m0 = s.mass()
+    for _ in range(120):
+        s.step()
+        assert np.all(s.q[0] >= 0.0)
+        assert np.all(np.isfinite(s.q))
+    assert sum(fc[2] for fc in s.flag_counts) == 0
+    assert abs(s.mass() - m0) / m0 < 1e-12
+    pp_tot = sum(fc[0] for fc in s.flag_counts)
+    assert pp_tot[1] > 0 and pp_tot[2] > 0

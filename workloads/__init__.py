@@ -1,0 +1,339 @@
+"""Seeded synthetic inputs for the DG shallow-water hot path.
+
+This module only builds inputs: conforming triangulations (vertex coordinates
+and counter-clockwise element-to-vertex lists) and the analytic bathymetry and
+initial-state functions that each side evaluates at its own nodes.  It holds
+none of the method's arithmetic (no reference element, no fluxes, no limiters,
+no time stepping) and is the only code shared by the FP64 oracle and the HIP
+path.
+
+Workloads (all seeded with ``numpy.random.default_rng(seed)``):
+
+* ``c1``  unit square, 16x16 cells split in two, N=3, flat bed, Gaussian hump
+          on depth 1, reflective walls, 200 AB3 steps at CFL 0.5, limiters on.
+* ``c2``  unit square, 256x256 jittered cells (131072 triangles), N=4,
+          sloping beach B = 0.8x plus eight Gaussian bumps, still level 0.5,
+          wet/dry, 500 steps.
+* ``c3``  [0,4]x[0,1] in four bands whose cell size halves per band
+          (496098 triangles), N=3, B = 0.9 (x/4)^2, right-going N-wave,
+          100 coarse steps of multi-rate AB3.
+* ``c4``  [0,2]x[0,1], 1024x512 jittered cells (1048576 triangles), N=5,
+          smooth random bed of 16 Fourier modes, fully wet, 300 steps.
+* ``c5``  ensemble of 64 jittered unit squares with log-uniform sizes in
+          [1e4, 2e5] triangles, N=3, per-instance beach slope and hump,
+          200 steps each.
+
+Bathymetry ``B`` is bed elevation; the free surface is ``eta = h + B``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+G_DEFAULT = 9.81
+
+
+@dataclass
+class Instance:
+    """One triangulated domain with its analytic data."""
+
+    vx: np.ndarray            # (Nv,) float64
+    vy: np.ndarray            # (Nv,) float64
+    etov: np.ndarray          # (K, 3) int32, counter-clockwise
+    bathymetry: Callable[[np.ndarray, np.ndarray], np.ndarray]
+    initial: Callable[[np.ndarray, np.ndarray], tuple]   # -> (h, hu, hv)
+    label: str = ""
+
+
+@dataclass
+class Workload:
+    name: str
+    N: int
+    instances: List[Instance]
+    steps: int
+    cfl: float = 0.5
+    g: float = G_DEFAULT
+    limiters: bool = True
+    max_levels: int = 1
+    seed: int = 0
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_elements(self) -> int:
+        return int(sum(inst.etov.shape[0] for inst in self.instances))
+
+    @property
+    def Np(self) -> int:
+        return (self.N + 1) * (self.N + 2) // 2
+
+
+# --------------------------------------------------------------------------
+# triangulations
+# --------------------------------------------------------------------------
+
+def structured_mesh(nx: int, ny: int, x0: float, x1: float, y0: float, y1: float,
+                    jitter: float = 0.0, rng: Optional[np.random.Generator] = None):
+    """nx-by-ny cells on [x0,x1]x[y0,y1]; each cell is cut along its
+    lower-left to upper-right diagonal into (v00, v10, v11) and (v00, v11, v01).
+
+    Vertices are numbered row-major (index j*(nx+1)+i), cells row-major, two
+    triangles per cell.  With ``jitter > 0`` every interior vertex moves by
+    independent U[-jitter*dx, jitter*dx] and U[-jitter*dy, jitter*dy] offsets;
+    boundary vertices stay fixed.
+    """
+    xs = np.linspace(x0, x1, nx + 1)
+    ys = np.linspace(y0, y1, ny + 1)
+    X, Y = np.meshgrid(xs, ys)            # (ny+1, nx+1)
+    vx = X.ravel().copy()
+    vy = Y.ravel().copy()
+    if jitter > 0.0:
+        if rng is None:
+            raise ValueError("jitter needs an rng")
+        dx = (x1 - x0) / nx
+        dy = (y1 - y0) / ny
+        jx = rng.uniform(-jitter * dx, jitter * dx, size=(ny + 1, nx + 1))
+        jy = rng.uniform(-jitter * dy, jitter * dy, size=(ny + 1, nx + 1))
+        interior = np.zeros((ny + 1, nx + 1), dtype=bool)
+        interior[1:-1, 1:-1] = True
+        vx = vx + np.where(interior, jx, 0.0).ravel()
+        vy = vy + np.where(interior, jy, 0.0).ravel()
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    v00 = (j * (nx + 1) + i).ravel()
+    v10 = v00 + 1
+    v01 = v00 + (nx + 1)
+    v11 = v01 + 1
+    etov = np.empty((2 * nx * ny, 3), dtype=np.int32)
+    etov[0::2] = np.stack([v00, v10, v11], axis=1)
+    etov[1::2] = np.stack([v00, v11, v01], axis=1)
+    return vx, vy, etov
+
+
+def graded_band_mesh(n0: int, n_bands: int, height: float = 1.0):
+    """[0, n_bands] x [0, height] in unit-wide bands; band b holds
+    (n0*2^b) x (n0*2^b*height) square cells.  Interior cells are cut in two
+    as in :func:`structured_mesh`; the last cell column of every band except
+    the finest meets twice as many vertices on its right edge, so each such
+    cell is cut into three triangles (v00,v10,m), (v00,m,v01), (v01,m,v11)
+    with m the midpoint vertex of its right edge.  Element order: band by
+    band, then row-major.
+    """
+    vx_list, vy_list = [], []
+    etov_list = []
+    vid = {}
+
+    def vertex(x: float, y: float) -> int:
+        # exact keys: every coordinate is a dyadic rational times 1/n0
+        key = (round(x * n0 * 2 ** (n_bands + 1)), round(y * n0 * 2 ** (n_bands + 1)))
+        idx = vid.get(key)
+        if idx is None:
+            idx = len(vx_list)
+            vid[key] = idx
+            vx_list.append(x)
+            vy_list.append(y)
+        return idx
+
+    for b in range(n_bands):
+        n = n0 * 2 ** b
+        ny = int(round(n * height))
+        h = 1.0 / n
+        for j in range(ny):
+            for i in range(n):
+                xa, xb = b + i * h, b + (i + 1) * h
+                ya, yb = j * h, (j + 1) * h
+                v00, v10 = vertex(xa, ya), vertex(xb, ya)
+                v01, v11 = vertex(xa, yb), vertex(xb, yb)
+                if i == n - 1 and b < n_bands - 1:
+                    m = vertex(xb, 0.5 * (ya + yb))
+                    etov_list += [(v00, v10, m), (v00, m, v01), (v01, m, v11)]
+                else:
+                    etov_list += [(v00, v10, v11), (v00, v11, v01)]
+    return (np.asarray(vx_list, dtype=np.float64), np.asarray(vy_list, dtype=np.float64),
+            np.asarray(etov_list, dtype=np.int32))
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def _zeros_like(x):
+    return np.zeros_like(np.asarray(x, dtype=np.float64))
+
+
+def c1(nx: int = 16) -> Workload:
+    vx, vy, etov = structured_mesh(nx, nx, 0.0, 1.0, 0.0, 1.0)
+
+    def bath(x, y):
+        return _zeros_like(x)
+
+    def init(x, y):
+        h = 1.0 + 0.1 * np.exp(-100.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2))
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload("c1", 3, [Instance(vx, vy, etov, bath, init, "c1")], steps=200,
+                    cfl=0.5, seed=1,
+                    notes="unit square 16x16x2, N=3, flat bed, Gaussian hump on depth 1")
+
+
+def beach_bathymetry(rng: np.random.Generator, n_bumps: int = 8, slope: float = 0.8,
+                     amp: float = 0.05, width: float = 0.05):
+    cx = rng.uniform(0.0, 1.0, size=n_bumps)
+    cy = rng.uniform(0.0, 1.0, size=n_bumps)
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        b = slope * x
+        for k in range(n_bumps):
+            b = b + amp * np.exp(-((x - cx[k]) ** 2 + (y - cy[k]) ** 2) / width ** 2)
+        return b
+
+    return bath, (cx, cy)
+
+
+def c2(n: int = 256, seed: int = 2) -> Workload:
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=0.2, rng=rng)
+    bath, _ = beach_bathymetry(rng)
+
+    def init(x, y):
+        eta = 0.5 + 0.05 * np.exp(-100.0 * ((x - 0.6) ** 2 + (y - 0.5) ** 2))
+        h = np.maximum(0.0, eta - bath(x, y))
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload("c2", 4, [Instance(vx, vy, etov, bath, init, "c2")], steps=500,
+                    cfl=0.5, seed=seed,
+                    notes=f"unit square {n}x{n}x2 jittered, N=4, beach 0.8x + 8 bumps, "
+                          "still level 0.5, hump 0.05 at (0.6,0.5), wet/dry")
+
+
+def c3(n0: int = 54, seed: int = 3, n_bands: int = 4) -> Workload:
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = graded_band_mesh(n0, n_bands)
+    xc = rng.uniform(0.4, 0.6)
+    w = rng.uniform(0.05, 0.1)
+    g = G_DEFAULT
+    L = float(n_bands)
+
+    def bath(x, y):
+        return 0.9 * (np.asarray(x, dtype=np.float64) / L) ** 2
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        d = 1.0 - bath(x, y)
+        z = (x - xc) / w
+        etap = -0.02 * z * np.exp(0.5 - 0.5 * z * z)
+        return d + etap, etap * np.sqrt(g * d), _zeros_like(x)
+
+    return Workload("c3", 3, [Instance(vx, vy, etov, bath, init, "c3")], steps=100,
+                    cfl=0.5, max_levels=n_bands, seed=seed,
+                    notes=f"graded bands n0={n0}, N=3, B=0.9(x/4)^2, N-wave xc={xc:.4f} w={w:.4f}",
+                    extra={"xc": xc, "w": w})
+
+
+def fourier_bathymetry(rng: np.random.Generator, n_modes: int = 16, amp: float = 0.1,
+                       mean_depth: float = 1.0, lx: float = 2.0, ly: float = 1.0):
+    k = rng.integers(1, 5, size=n_modes)
+    l = rng.integers(1, 5, size=n_modes)
+    a = rng.uniform(-1.0, 1.0, size=n_modes)
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+
+    def f(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        s = np.zeros(np.broadcast(x, y).shape)
+        for m in range(n_modes):
+            s = s + a[m] * np.cos(2.0 * np.pi * (k[m] * x / lx + l[m] * y / ly) + phi[m])
+        return s
+
+    # normalisation over a fixed lattice, independent of any node set
+    gx, gy = np.meshgrid(np.linspace(0.0, lx, 1025), np.linspace(0.0, ly, 513))
+    fmax = float(np.max(np.abs(f(gx, gy))))
+
+    def bath(x, y):
+        return -mean_depth + amp * f(x, y) / fmax
+
+    return bath
+
+
+def c4(nx: int = 1024, ny: int = 512, seed: int = 4) -> Workload:
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(nx, ny, 0.0, 2.0, 0.0, 1.0, jitter=0.2, rng=rng)
+    bath = fourier_bathymetry(rng)
+
+    def init(x, y):
+        eta = 0.1 * np.exp(-100.0 * ((x - 1.0) ** 2 + (y - 0.5) ** 2))
+        return eta - bath(x, y), _zeros_like(x), _zeros_like(x)
+
+    return Workload("c4", 5, [Instance(vx, vy, etov, bath, init, "c4")], steps=300,
+                    cfl=0.5, seed=seed,
+                    notes=f"[0,2]x[0,1] {nx}x{ny}x2 jittered, N=5, 16 Fourier modes amp 0.1 "
+                          "about depth 1, hump 0.1 at (1,0.5), fully wet")
+
+
+def c5(n_inst: int = 64, seed: int = 5, kmin: float = 1e4, kmax: float = 2e5) -> Workload:
+    rng = np.random.default_rng(seed)
+    ktil = np.exp(rng.uniform(np.log(kmin), np.log(kmax), size=n_inst))
+    ns = np.maximum(2, np.rint(np.sqrt(ktil / 2.0)).astype(int))
+    insts = []
+    for i in range(n_inst):
+        n = int(ns[i])
+        vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=0.2, rng=rng)
+        slope = rng.uniform(0.3, 1.0)
+        amp = rng.uniform(0.01, 0.1)
+        cx, cy = rng.uniform(0.0, 1.0, size=2)
+
+        def bath(x, y, slope=slope):
+            return slope * np.asarray(x, dtype=np.float64)
+
+        def init(x, y, slope=slope, amp=amp, cx=cx, cy=cy):
+            x = np.asarray(x, dtype=np.float64)
+            y = np.asarray(y, dtype=np.float64)
+            eta = 0.5 + amp * np.exp(-100.0 * ((x - cx) ** 2 + (y - cy) ** 2))
+            return np.maximum(0.0, eta - slope * x), _zeros_like(x), _zeros_like(x)
+
+        insts.append(Instance(vx, vy, etov, bath, init, f"c5[{i}] n={n}"))
+    return Workload("c5", 3, insts, steps=200, cfl=0.5, seed=seed,
+                    notes="64 jittered unit squares, log-uniform sizes, beach + hump each")
+
+
+def lake_at_rest(n: int = 4, N: int = 3, jitter: float = 0.2, seed: int = 11,
+                 level: float = 1.0) -> Workload:
+    """Fully wet still water over a non-constant bed (exact steady state)."""
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=jitter, rng=rng)
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return 0.2 * np.sin(2.0 * np.pi * x) * np.cos(np.pi * y) + 0.1 * x * y
+
+    def init(x, y):
+        return level - bath(x, y), _zeros_like(x), _zeros_like(x)
+
+    return Workload("lake", N, [Instance(vx, vy, etov, bath, init, "lake")], steps=50,
+                    cfl=0.5, seed=seed, notes="lake at rest")
+
+
+def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Workload:
+    """A small beach with a hump straddling the shoreline (exercises both limiters)."""
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=0.2, rng=rng)
+    bath, _ = beach_bathymetry(rng, n_bumps=2)
+
+    def init(x, y):
+        eta = 0.5 + 0.05 * np.exp(-100.0 * ((x - 0.6) ** 2 + (y - 0.5) ** 2))
+        return np.maximum(0.0, eta - bath(x, y)), _zeros_like(x), _zeros_like(x)
+
+    return Workload("wetdry", N, [Instance(vx, vy, etov, bath, init, "wetdry")], steps=steps,
+                    cfl=0.5, seed=seed, notes="small beach")
+
+
+WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def get(name: str, **kw) -> Workload:
+    return WORKLOADS[name](**kw)
