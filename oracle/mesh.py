@@ -164,13 +164,11 @@ def time_step(mesh: Mesh, N: int, cfl: float, a_max: float) -> float:
     return cfl * mesh.inradius.min() / ((N + 1) ** 2 * max(a_max, 1e-12))
 
 
-def wave_speed(h, hu, hv, g: float, h0: float) -> float:
-    """max |(u,v)| + sqrt(g h) over the nodes (velocity zero where h <= h0)."""
-    wet = h > h0
-    hs = np.where(wet, h, 1.0)
-    u = np.where(wet, hu / hs, 0.0)
-    v = np.where(wet, hv / hs, 0.0)
-    return float(np.max(np.hypot(u, v) + np.sqrt(g * np.maximum(h, 0.0))))
+def wave_speed(h, hu, hv, g: float, hvel: float) -> float:
+    """max |(u,v)| + sqrt(g h) over the nodes, with the desingularised
+    velocity 2 h m / (h^2 + max(h^2, hvel^2))."""
+    f = 2.0 * h / (h * h + np.maximum(h * h, hvel * hvel))
+    return float(np.max(np.hypot(hu * f, hv * f) + np.sqrt(g * np.maximum(h, 0.0))))
 
 
 @dataclass

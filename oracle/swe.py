@@ -9,7 +9,11 @@ form with the numerical flux of Section 5.1:
 
     R(Q) = -(d/dx F + d/dy G) + S + LIFT [ Fscale (F(Q-).n - F*.n) ]
 
-* velocities u = hu/h, v = hv/h where h > h0, zero elsewhere;
+* velocities u = 2 h hu / (h^2 + max(h^2, hvel^2)) (likewise v): hu/h where
+  h >= hvel, continuous down to zero at h = 0.  The paper does not say how
+  the velocity is formed near dry nodes; a continuous form has no branch for
+  rounding to flip, and hvel above the positivity limiter's vertex value h0
+  keeps the velocity at that vertex bounded;
 * S is the bathymetry source -g h grad B written as
   -g eta grad B + (g/2) grad(B^2) with eta = h + B (the splitting of the
   Xing & Shu paper the well-balanced flux is taken from), which keeps the
@@ -64,6 +68,7 @@ class Params:
     cfl: float = 0.5
     h0: float = 1e-5          # dry threshold
     eps: float = 1e-5         # positivity-limiter trigger
+    hvel: float = 1e-3        # depth below which velocities are desingularised
     tvb_M: float = 10.0
     tvb_nu: float = 1.5
     pp: bool = True
@@ -118,7 +123,7 @@ class Solver:
         self.B = np.array(B, dtype=np.float64)
         q = np.stack([np.asarray(h, np.float64), np.asarray(hu, np.float64),
                       np.asarray(hv, np.float64)]).copy()
-        a_max = wave_speed(q[0], q[1], q[2], self.p.g, self.p.h0)
+        a_max = wave_speed(q[0], q[1], q[2], self.p.g, self.p.hvel)
         self.dt_min = time_step(self.mesh, self.N, self.p.cfl, a_max)
         if limit:
             q, self.flags = self.limit(q)
@@ -144,9 +149,11 @@ class Solver:
         return m.ry[:, None] * self.ddr(f) + m.sy[:, None] * self.dds(f)
 
     def velocity(self, h, hu, hv):
-        wet = h > self.p.h0
-        hs = np.where(wet, h, 1.0)
-        return np.where(wet, hu / hs, 0.0), np.where(wet, hv / hs, 0.0)
+        """Desingularised velocity 2 h m / (h^2 + max(h^2, hvel^2)): equal to
+        m/h for h >= hvel, continuous in h, zero at h = 0."""
+        den = h * h + np.maximum(h * h, self.p.hvel ** 2)
+        f = 2.0 * h / den
+        return hu * f, hv * f
 
     def traces(self, q, B, t, qP_override=None):
         """Interior (-) and exterior (+) traces at the 3*Nfp face nodes."""

@@ -13,7 +13,8 @@ Workloads (all seeded with ``numpy.random.default_rng(seed)``):
           on depth 1, reflective walls, 200 AB3 steps at CFL 0.5, limiters on.
 * ``c2``  unit square, 256x256 jittered cells (131072 triangles), N=4,
           sloping beach B = 0.8x plus eight Gaussian bumps, still level 0.5,
-          wet/dry, 500 steps.
+          wet/dry, 500 steps at CFL 0.2 (AB3 at a wet/dry front is unstable
+          at 0.3 and above).
 * ``c3``  [0,4]x[0,1] in four bands whose cell size halves per band
           (496098 triangles), N=3, B = 0.9 (x/4)^2, right-going N-wave,
           100 coarse steps of multi-rate AB3.
@@ -205,7 +206,7 @@ def c2(n: int = 256, seed: int = 2) -> Workload:
         return h, _zeros_like(x), _zeros_like(x)
 
     return Workload("c2", 4, [Instance(vx, vy, etov, bath, init, "c2")], steps=500,
-                    cfl=0.5, seed=seed,
+                    cfl=0.2, seed=seed,
                     notes=f"unit square {n}x{n}x2 jittered, N=4, beach 0.8x + 8 bumps, "
                           "still level 0.5, hump 0.05 at (0.6,0.5), wet/dry")
 
@@ -296,7 +297,7 @@ def c5(n_inst: int = 64, seed: int = 5, kmin: float = 1e4, kmax: float = 2e5) ->
             return np.maximum(0.0, eta - slope * x), _zeros_like(x), _zeros_like(x)
 
         insts.append(Instance(vx, vy, etov, bath, init, f"c5[{i}] n={n}"))
-    return Workload("c5", 3, insts, steps=200, cfl=0.5, seed=seed,
+    return Workload("c5", 3, insts, steps=200, cfl=0.2, seed=seed,
                     notes="64 jittered unit squares, log-uniform sizes, beach + hump each")
 
 
@@ -329,7 +330,7 @@ def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Wor
         return np.maximum(0.0, eta - bath(x, y)), _zeros_like(x), _zeros_like(x)
 
     return Workload("wetdry", N, [Instance(vx, vy, etov, bath, init, "wetdry")], steps=steps,
-                    cfl=0.5, seed=seed, notes="small beach")
+                    cfl=0.2, seed=seed, notes="small beach")
 
 
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
