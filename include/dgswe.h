@@ -1,0 +1,220 @@
+/*
+ * dgswe.h - C ABI of the MI355X (gfx950) nodal discontinuous Galerkin solver
+ * for the 2D nonlinear shallow water equations on triangles.
+ *
+ * Method (Gandham, Medina & Warburton, "GPU accelerated discontinuous
+ * Galerkin methods for shallow water equations"):
+ *   - conservative SWE with bathymetry source            Section 2, Eq. 2.1-2.3
+ *   - nodal DG on Warp & Blend nodes, strong form with
+ *     the well-balanced local Lax-Friedrichs flux          Section 3, Eq. 3.2-3.3;
+ *                                                          Section 5.1, Eq. 5.1-5.2
+ *   - multi-rate Adams-Bashforth 3 over levels that step
+ *     with 2^(l-1) dt_min                                  Section 4, Eq. 4.1, Algorithm 4.1
+ *   - positivity limiter, then positivity-modified TVB
+ *     limiter after every update                           Algorithms 5.1, 5.2; Eq. 5.3
+ *
+ * Conventions for every call:
+ *   - Return value: DG_OK (0) or a negative DG_E* code; the message of the
+ *     last failure on the calling thread is returned by dg_last_error().
+ *   - Host arrays are owned by the caller and are only read or written during
+ *     the call; nothing keeps a pointer to them.
+ *   - Device memory is owned by the caller: dg_query_sizes() says how many
+ *     bytes the solver needs, the caller allocates one device buffer of at
+ *     least that size (256-byte aligned) and hands it over with dg_bind().
+ *     The library never frees it.  The solver handle is owned by the caller
+ *     and released with dg_destroy().
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     dg_advance() only enqueues work; dg_get_* calls that return device
+ *     data synchronise the stream before returning.
+ *   - Element order: arrays indexed by element use the caller's element
+ *     order of the instance (the library reorders internally).  Nodal arrays
+ *     are [K][Np] row-major, node order as returned by dg_node_coords().
+ *   - A handle is not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef DGSWE_H
+#define DGSWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DG_OK          0
+#define DG_EINVAL     -1  /* bad argument (null pointer, out-of-range value)       */
+#define DG_EMESH      -2  /* malformed mesh: clockwise/degenerate element, face    */
+                          /* shared by more than two elements, inconsistent faces  */
+#define DG_ENOMEM     -3  /* host allocation failed or bound buffer too small      */
+#define DG_EDEVICE    -4  /* a HIP runtime call failed                             */
+#define DG_ENOTBOUND  -5  /* device buffer not bound, or state not set             */
+#define DG_ENUMERIC   -6  /* non-finite value in input or state                    */
+#define DG_ESTATE     -7  /* call not valid in the current state                   */
+
+/* contraction / kernel path (dg_params.precision) */
+#define DG_PLAIN_FP32     0  /* separate RHS, update and limiter kernels, FP32 VALU  */
+#define DG_FUSED_FP32     1  /* fused RHS+AB3+positivity kernel, FP32 VALU matvecs   */
+#define DG_FUSED_MFMA32   2  /* fused kernel, [Dr Ds LIFT] contraction on FP32 MFMA  */
+#define DG_FUSED_BF16X3   3  /* fused kernel, BF16 hi/lo split MFMA, FP32 accumulate */
+
+/* limiter switches (dg_params.limiter_mask) */
+#define DG_LIMIT_PP   1      /* positivity limiter, Algorithm 5.2         */
+#define DG_LIMIT_TVB  2      /* TVB limiter with Eq. 5.3                  */
+
+/* per-element flag byte: bits 0-1 positivity code, bits 2-3 TVB code */
+#define DG_PP_KEEP     0     /* min nodal depth above eps: untouched      */
+#define DG_PP_SCALED   1     /* P1 projection scaled about the mean       */
+#define DG_PP_DRY      2     /* mean depth below h0: element set dry      */
+#define DG_TVB_SKIPPED 0     /* dry element or neighbour of a dry element */
+#define DG_TVB_KEPT    1     /* no characteristic component limited       */
+#define DG_TVB_LIMITED 2     /* limited to P1                             */
+#define DG_TVB_POSITIVE 3    /* limited, depth increments rescaled by Eq. 5.3 */
+
+typedef struct dg_solver dg_solver;
+
+/* One triangulated instance.  vx, vy: n_vertices coordinates.  etov:
+ * n_elements x 3 vertex indices, counter-clockwise.  Faces not shared with a
+ * second element are reflective walls.  Face f of an element joins its
+ * vertices f and f+1 (mod 3). */
+typedef struct dg_mesh_desc {
+    int32_t n_vertices;
+    const double* vx;
+    const double* vy;
+    int32_t n_elements;
+    const int32_t* etov;
+} dg_mesh_desc;
+
+typedef struct dg_params {
+    int32_t N;              /* polynomial degree, 1..6                                */
+    double g;               /* gravity                                                */
+    double cfl;             /* dt_k = cfl * r_k / ((N+1)^2 a_max), Eq. 4.1             */
+    double h0;              /* dry threshold of Algorithm 5.2 and Eq. 5.3 (> 0)        */
+    double eps;             /* positivity trigger: limit when min nodal h <= eps      */
+    double hvel;            /* velocity u = 2 h hu / (h^2 + max(h^2, hvel^2)): hu/h   */
+                            /* for h >= hvel, continuous to 0 at h = 0 (> 0)          */
+    double tvb_M;           /* TVB constant M (minmod bypass when |a| <= M d_K^2)      */
+    double tvb_nu;          /* TVB factor on the neighbour difference (>= 1)          */
+    int32_t limiter_mask;   /* DG_LIMIT_* bits                                        */
+    int32_t max_levels;     /* multi-rate levels (1 = single rate AB3), 1..8          */
+    int32_t precision;      /* DG_PLAIN_FP32 .. DG_FUSED_BF16X3                        */
+    int32_t dry_literal;    /* 1: dry element gets h = h0 (Algorithm 5.2 as printed); */
+                            /* 0: h = max(mean, 0), which conserves mass              */
+    int32_t use_graph;      /* 1: replay dg_advance steps from a captured hipGraph    */
+    int32_t elems_per_block;/* 0 = default for N and path                             */
+} dg_params;
+
+/* Fill *p with the defaults: g 9.81, cfl 0.5, h0 = eps = 1e-5, hvel 1e-3, M 10, nu 1.5,
+ * both limiters, single rate, DG_FUSED_FP32, mass-conserving dry branch,
+ * graphs on. */
+int32_t dg_default_params(int32_t N, dg_params* p);
+
+/* Validate and set up n_inst instances (n_inst > 1: an ensemble advanced
+ * together, each with its own dt): reference element, connectivity,
+ * geometry, levels, TVB stencil.  Host only; no device work.
+ * Errors: DG_EINVAL (null/size), DG_EMESH (see above), DG_ENOMEM. */
+int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p,
+                  dg_solver** out);
+
+/* Release the handle (not the caller's device buffer).  NULL is a no-op. */
+void dg_destroy(dg_solver* h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* dg_last_error(void);
+
+/* Sizes: total elements, Np, Nfp, and the device bytes dg_bind needs. */
+int32_t dg_query_sizes(const dg_solver* h, int64_t* total_elements, int32_t* Np,
+                       int32_t* Nfp, int64_t* workspace_bytes);
+
+/* Bind caller-owned device memory (>= workspace_bytes, 256-byte aligned) on
+ * the current HIP device, and upload the static setup data on `stream`.
+ * Errors: DG_EINVAL (null/misaligned), DG_ENOMEM (too small), DG_EDEVICE. */
+int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* stream);
+
+/* Number of elements of instance `inst`. */
+int32_t dg_instance_elements(const dg_solver* h, int32_t inst, int32_t* K);
+
+/* Physical node coordinates of instance `inst`, [K][Np] each (host). */
+int32_t dg_node_coords(const dg_solver* h, int32_t inst, double* x, double* y);
+
+/* Reference nodes r, s (Np each) and operators, row-major, FP64:
+ * which = 0: Dr (Np x Np), 1: Ds (Np x Np), 2: LIFT (Np x 3Nfp),
+ * 3: mass matrix (Np x Np), 4: cell-integral weights w (Np),
+ * 5: face node indices (3 x Nfp, as doubles). */
+int32_t dg_reference(const dg_solver* h, int32_t which, double* out);
+int32_t dg_reference_nodes(const dg_solver* h, double* r, double* s);
+
+/* Bed elevation B at the nodes of instance `inst` ([K][Np], host). */
+int32_t dg_set_bathymetry(dg_solver* h, int32_t inst, const double* B);
+
+/* Initial depth and momenta of instance `inst` ([K][Np] each, host, FP64).
+ * The time step of the instance is set from the wave speed
+ * max |u| + sqrt(g h) of this data (Eq. 4.1).  Once every instance has its
+ * state (and bathymetry), the first dg_advance applies Q0 = TVB(PP(Q0))
+ * (Algorithm 5.1, first line); setting any state resets the time stepping.
+ * Errors: DG_ENOTBOUND (no buffer bound), DG_ENUMERIC (non-finite or
+ * negative depth), DG_EINVAL. */
+int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double* hu,
+                     const double* hv, void* stream);
+
+/* Apply the initial limiting now (otherwise done by the first dg_advance). */
+int32_t dg_prepare(dg_solver* h, void* stream);
+
+/* Enqueue n_steps steps on `stream`: single-rate AB3 steps, or with
+ * max_levels > 1 coarse steps of multi-rate AB3 (2^(L-1) ticks of dt_min).
+ * Each step: RHS, AB update, positivity limiter, TVB limiter.
+ * Errors: DG_ENOTBOUND (state not set), DG_EDEVICE. */
+int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
+
+/* Current state of instance `inst` as FP64 depth and momenta ([K][Np]).
+ * Synchronises `stream`. */
+int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double* hv,
+                     void* stream);
+
+/* Face connectivity of instance `inst` in its own element numbering:
+ * etoe[K][3] (the element itself for a wall face), etof[K][3]. */
+int32_t dg_get_connectivity(const dg_solver* h, int32_t inst, int32_t* etoe, int8_t* etof);
+
+/* Multi-rate level (1 = finest) of every element of instance `inst`, and the
+ * instance's dt_min (0 before its state is set). */
+int32_t dg_get_levels(const dg_solver* h, int32_t inst, int8_t* level, double* dt_min);
+
+/* TVB stencil of instance `inst`: pair[K][3][2] face indices used for edge i,
+ * alpha[K][3][2] coefficients (Section 5.3). */
+int32_t dg_get_tvb_stencil(const dg_solver* h, int32_t inst, int8_t* pair, double* alpha);
+
+/* Per-element flag bytes (see DG_PP_* / DG_TVB_*) from the last limiter pass.
+ * Synchronises `stream`. */
+int32_t dg_get_flags(dg_solver* h, int32_t inst, uint8_t* flags, void* stream);
+
+typedef struct dg_diag {
+    double mass;            /* sum_k J_k w.h_k (FP64)                        */
+    double min_depth;       /* min nodal h                                    */
+    double time;            /* simulated time of the instance                 */
+    int64_t steps;          /* steps (coarse steps) taken since set_state     */
+    int64_t negative_means; /* positivity-limiter passes that met mean h < 0  */
+    int64_t pp_counts[3];   /* elements per DG_PP_* code, last limiter pass   */
+    int64_t tvb_counts[4];  /* elements per DG_TVB_* code, last limiter pass  */
+} dg_diag;
+
+/* Deterministic FP64 reductions over instance `inst`.  Synchronises `stream`. */
+int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream);
+
+/* Checkpoint: the full time-stepping state (states, RHS history, half-step
+ * traces, counters) as an opaque byte blob; dg_checkpoint_bytes gives the
+ * size.  Restoring onto a solver created with the same meshes and params
+ * continues bit-identically.  Both synchronise `stream`. */
+int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes);
+int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream);
+int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* stream);
+
+/* Device timing of the last dg_advance when the solver was created with
+ * profiling on: average duration (microseconds) of the dominant fused kernel
+ * measured with HIP events on the stream it runs on. */
+int32_t dg_set_profiling(dg_solver* h, int32_t on);
+int32_t dg_kernel_timing(const dg_solver* h, double* avg_us, int64_t* launches,
+                         int64_t* elements_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGSWE_H */

@@ -1,0 +1,938 @@
+// C ABI of the DG shallow-water solver: setup, device binding, time stepping,
+// read-back.  Host work is FP64; the device path is the HIP step/TVB kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dgswe.h"
+#include "dg_launch.hpp"
+#include "host_mesh.hpp"
+#include "host_refelem.hpp"
+
+using namespace dgswe;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(call)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) return fail(DG_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t Q[2], R[3], half, means, devs, flags, counters;   // dynamic (checkpointed)
+    size_t dyn_begin, dyn_end;
+    size_t B, geo, conn, stencil;
+    size_t Dr, Ds, LIFT, Amfma, fmask, nodeface, wh, pmid, phi, wfull;
+    size_t diag_partial, diag_out;
+    size_t total;
+};
+
+struct Inst {
+    HostMesh mesh;
+    int offset = 0;          // first global (unsorted) element index
+    bool has_B = false, has_state = false;
+    double dt_min = 0.0, a_max = 0.0, time = 0.0;
+    // Vertical datum of the instance: the device stores eta - datum and
+    // B - datum in FP32.  Every formula of the scheme depends on depths and
+    // surface-level differences only, so the shift changes nothing but the
+    // FP32 rounding of the stored surface level, which shrinks with |eta - datum|.
+    float datum = 0.f;
+};
+
+}  // namespace
+
+struct dg_solver {
+    dg_params p{};
+    RefElement re;
+    std::vector<Inst> inst;
+    int K = 0, Np = 0, Nfp = 0, nF = 0, L = 1;
+    std::vector<int> perm, inv, inst_of;     // sorted -> global, global -> sorted
+    std::vector<int> lev_begin, lev_end;     // per level (0-based) in sorted order
+    Layout lay{};
+    char* ws = nullptr;
+    bool bound = false, prepared = false;
+    int device = 0;
+    // host staging (sorted order, FP32)
+    std::vector<float> geo, stencil, Bh, Qh;   // Qh: [3][K*Np]; Bh, Qh[0] relative to the datum
+    std::vector<double> B64;                   // bed elevation, FP64, sorted order
+    std::vector<int> conn;
+    // time stepping state
+    int parity[kMaxLevels] = {0}, head[kMaxLevels] = {0}, nhist[kMaxLevels] = {0};
+    long long steps = 0;
+    // execution
+    hipStream_t exec = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_key[3 * kMaxLevels] = {0};
+    bool have_graph = false;
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    size_t prof_used = 0;
+    double prof_avg_us = 0.0;
+    long long prof_launches = 0, prof_elems = 0;
+};
+
+// ---------------------------------------------------------------------------
+static const float kAB[3][3] = {{1.f, 0.f, 0.f}, {1.5f, -0.5f, 0.f},
+                                {23.f / 12.f, -16.f / 12.f, 5.f / 12.f}};
+static const float kHalf[3][3] = {{0.5f, 0.f, 0.f}, {5.f / 8.f, -1.f / 8.f, 0.f},
+                                  {17.f / 24.f, -7.f / 24.f, 2.f / 24.f}};
+
+static int engine_of(int precision) {
+    switch (precision) {
+        case DG_FUSED_MFMA32: return ENGINE_MFMA_F32;
+        case DG_FUSED_BF16X3: return ENGINE_MFMA_BF16X3;
+        default: return ENGINE_VALU;
+    }
+}
+
+static void compute_layout(dg_solver* h) {
+    Layout& l = h->lay;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t KNp = size_t(h->K) * h->Np, KnF = size_t(h->K) * h->nF;
+    l.dyn_begin = o;
+    l.Q[0] = take(3 * KNp * 4);
+    l.Q[1] = take(3 * KNp * 4);
+    for (int s = 0; s < 3; ++s) l.R[s] = take(3 * KNp * 4);
+    l.half = take(h->L > 1 ? 3 * KnF * 4 : 0);
+    l.means = take(3 * size_t(h->K) * 8);
+    l.devs = take(9 * size_t(h->K) * 4);
+    l.flags = take(size_t(h->K));
+    l.counters = take(64);
+    l.dyn_end = o;
+    l.B = take(KNp * 4);
+    l.geo = take(size_t(h->K) * 64);
+    l.conn = take(size_t(h->K) * 16);
+    l.stencil = take(size_t(h->K) * 64);
+    const int Np = h->Np, nF = h->nF;
+    l.Dr = take(size_t(Np) * Np * 4);
+    l.Ds = take(size_t(Np) * Np * 4);
+    l.LIFT = take(size_t(Np) * nF * 4);
+    l.Amfma = take(size_t(64) * 256 * 4 * 2);
+    l.fmask = take(size_t(nF) * 4);
+    l.nodeface = take(size_t(Np) * 2 * 4);
+    l.wh = take(size_t(Np) * 8);
+    l.pmid = take(3 * size_t(Np) * 8);
+    l.phi = take(3 * size_t(Np) * 8);
+    l.wfull = take(size_t(Np) * 8);
+    l.diag_partial = take(256 * 16 * 8);
+    l.diag_out = take(16 * 8);
+    l.total = o;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+int32_t dg_default_params(int32_t N, dg_params* p) {
+    if (!p) return fail(DG_EINVAL, "null params");
+    std::memset(p, 0, sizeof(*p));
+    p->N = N;
+    p->g = 9.81;
+    p->cfl = 0.5;
+    p->h0 = 1e-5;
+    p->eps = 1e-5;
+    p->hvel = 1e-3;
+    p->tvb_M = 10.0;
+    p->tvb_nu = 1.5;
+    p->limiter_mask = DG_LIMIT_PP | DG_LIMIT_TVB;
+    p->max_levels = 1;
+    p->precision = DG_FUSED_FP32;
+    p->dry_literal = 0;
+    p->use_graph = 1;
+    p->elems_per_block = 0;
+    return DG_OK;
+}
+
+int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p, dg_solver** out) {
+    if (!meshes || !p || !out || n_inst < 1) return fail(DG_EINVAL, "null argument or n_inst < 1");
+    *out = nullptr;
+    if (p->N < 1 || p->N > 6) return fail(DG_EINVAL, "N must be in 1..6");
+    if (!(p->g > 0) || !(p->cfl > 0) || !(p->h0 > 0) || !(p->eps >= 0) || !(p->hvel > 0) ||
+        !(p->tvb_M >= 0) ||
+        !(p->tvb_nu >= 1.0))
+        return fail(DG_EINVAL, "bad physical or limiter parameter");
+    if (p->max_levels < 1 || p->max_levels > kMaxLevels)
+        return fail(DG_EINVAL, "max_levels must be in 1..6");
+    if (p->precision < DG_PLAIN_FP32 || p->precision > DG_FUSED_BF16X3)
+        return fail(DG_EINVAL, "unknown precision/path");
+    if (p->precision == DG_FUSED_MFMA32 || p->precision == DG_FUSED_BF16X3)
+        return fail(DG_EINVAL, "MFMA contraction paths are not available in this build");
+    std::unique_ptr<dg_solver> h;
+    try {
+        h.reset(new dg_solver());
+        h->p = *p;
+        h->re = build_reference(p->N);
+    } catch (const std::bad_alloc&) {
+        return fail(DG_ENOMEM, "out of host memory");
+    } catch (const std::exception& ex) {
+        return fail(DG_EINVAL, ex.what());
+    }
+    h->Np = h->re.Np;
+    h->Nfp = h->re.Nfp;
+    h->nF = 3 * h->Nfp;
+    h->L = p->max_levels;
+    h->inst.resize(n_inst);
+    long long total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const dg_mesh_desc& m = meshes[i];
+        if (!m.vx || !m.vy || !m.etov || m.n_elements < 1 || m.n_vertices < 3)
+            return fail(DG_EINVAL, "instance " + std::to_string(i) + ": null or empty mesh");
+        std::string err;
+        try {
+            err = build_host_mesh(m.n_vertices, m.vx, m.vy, m.n_elements, m.etov, h->inst[i].mesh);
+        } catch (const std::bad_alloc&) {
+            return fail(DG_ENOMEM, "out of host memory");
+        }
+        if (!err.empty()) return fail(DG_EMESH, "instance " + std::to_string(i) + ": " + err);
+        assign_levels(h->inst[i].mesh, h->L);
+        build_tvb_stencil(h->inst[i].mesh);
+        h->inst[i].offset = int(total);
+        total += m.n_elements;
+    }
+    if (total > (1LL << 30)) return fail(DG_EINVAL, "too many elements");
+    h->K = int(total);
+    // sort by (level, instance, local index)
+    h->perm.resize(h->K);
+    h->inv.resize(h->K);
+    h->inst_of.resize(h->K);
+    std::vector<int> lev_g(h->K);
+    for (int i = 0; i < n_inst; ++i)
+        for (int k = 0; k < h->inst[i].mesh.K; ++k) lev_g[h->inst[i].offset + k] = h->inst[i].mesh.level[k];
+    int pos = 0;
+    h->lev_begin.assign(h->L, 0);
+    h->lev_end.assign(h->L, 0);
+    for (int l = 1; l <= h->L; ++l) {
+        h->lev_begin[l - 1] = pos;
+        for (int i = 0; i < n_inst; ++i)
+            for (int k = 0; k < h->inst[i].mesh.K; ++k) {
+                const int gidx = h->inst[i].offset + k;
+                if (lev_g[gidx] != l) continue;
+                h->perm[pos] = gidx;
+                h->inv[gidx] = pos;
+                h->inst_of[pos] = i;
+                ++pos;
+            }
+        h->lev_end[l - 1] = pos;
+    }
+    // static per-element device records
+    const int K = h->K;
+    h->geo.assign(size_t(K) * 16, 0.f);
+    h->conn.assign(size_t(K) * 4, 0);
+    h->stencil.assign(size_t(K) * 16, 0.f);
+    for (int s = 0; s < K; ++s) {
+        const int gidx = h->perm[s], i = h->inst_of[s];
+        const HostMesh& m = h->inst[i].mesh;
+        const int k = gidx - h->inst[i].offset;
+        float* gk = &h->geo[16 * size_t(s)];
+        gk[0] = float(m.rx[k]); gk[1] = float(m.ry[k]); gk[2] = float(m.sx[k]); gk[3] = float(m.sy[k]);
+        for (int f = 0; f < 3; ++f) {
+            gk[4 + f] = float(m.nx[3 * k + f]);
+            gk[7 + f] = float(m.ny[3 * k + f]);
+            gk[10 + f] = float(m.fscale[3 * k + f]);
+        }
+        gk[13] = float(m.J[k]);
+        gk[14] = 0.f;
+        int iid = i;
+        std::memcpy(&gk[15], &iid, 4);
+        int* cn = &h->conn[4 * size_t(s)];
+        int packed = 0;
+        for (int f = 0; f < 3; ++f) {
+            if (m.wall[3 * k + f]) {
+                cn[f] = -1;
+            } else {
+                cn[f] = h->inv[h->inst[i].offset + m.etoe[3 * k + f]];
+                packed |= (m.etof[3 * k + f] & 3) << (2 * f);
+            }
+        }
+        cn[3] = packed;
+        float* st = &h->stencil[16 * size_t(s)];
+        int pairs = 0;
+        for (int e = 0; e < 3; ++e) {
+            st[4 * e] = float(m.alpha[6 * k + 2 * e]);
+            st[4 * e + 1] = float(m.alpha[6 * k + 2 * e + 1]);
+            st[4 * e + 2] = float(m.dir[6 * k + 2 * e]);
+            st[4 * e + 3] = float(m.dir[6 * k + 2 * e + 1]);
+            pairs |= (m.pair[6 * k + 2 * e] & 3) << (4 * e);
+            pairs |= (m.pair[6 * k + 2 * e + 1] & 3) << (4 * e + 2);
+        }
+        st[12] = float(p->tvb_M * m.dk[k] * m.dk[k]);
+        std::memcpy(&st[13], &pairs, 4);
+    }
+    compute_layout(h.get());
+    *out = h.release();
+    return DG_OK;
+}
+
+void dg_destroy(dg_solver* h) {
+    if (!h) return;
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (auto& ev : h->prof_events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    if (h->exec) (void)hipStreamDestroy(h->exec);
+    delete h;
+}
+
+int32_t dg_query_sizes(const dg_solver* h, int64_t* total_elements, int32_t* Np, int32_t* Nfp,
+                       int64_t* workspace_bytes) {
+    if (!h) return fail(DG_EINVAL, "null handle");
+    if (total_elements) *total_elements = h->K;
+    if (Np) *Np = h->Np;
+    if (Nfp) *Nfp = h->Nfp;
+    if (workspace_bytes) *workspace_bytes = int64_t(h->lay.total);
+    return DG_OK;
+}
+
+int32_t dg_instance_elements(const dg_solver* h, int32_t inst, int32_t* K) {
+    if (!h || !K || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    *K = h->inst[inst].mesh.K;
+    return DG_OK;
+}
+
+int32_t dg_node_coords(const dg_solver* h, int32_t inst, double* x, double* y) {
+    if (!h || !x || !y || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    node_coords(h->inst[inst].mesh, h->re, x, y);
+    return DG_OK;
+}
+
+int32_t dg_reference_nodes(const dg_solver* h, double* r, double* s) {
+    if (!h || !r || !s) return fail(DG_EINVAL, "bad argument");
+    std::copy(h->re.r.begin(), h->re.r.end(), r);
+    std::copy(h->re.s.begin(), h->re.s.end(), s);
+    return DG_OK;
+}
+
+int32_t dg_reference(const dg_solver* h, int32_t which, double* out) {
+    if (!h || !out) return fail(DG_EINVAL, "bad argument");
+    const RefElement& re = h->re;
+    switch (which) {
+        case 0: std::copy(re.Dr.a.begin(), re.Dr.a.end(), out); break;
+        case 1: std::copy(re.Ds.a.begin(), re.Ds.a.end(), out); break;
+        case 2: std::copy(re.LIFT.a.begin(), re.LIFT.a.end(), out); break;
+        case 3: std::copy(re.M.a.begin(), re.M.a.end(), out); break;
+        case 4: std::copy(re.w.begin(), re.w.end(), out); break;
+        case 5:
+            for (size_t t = 0; t < re.fmask.size(); ++t) out[t] = re.fmask[t];
+            break;
+        default: return fail(DG_EINVAL, "unknown operator id");
+    }
+    return DG_OK;
+}
+
+int32_t dg_get_connectivity(const dg_solver* h, int32_t inst, int32_t* etoe, int8_t* etof) {
+    if (!h || !etoe || !etof || inst < 0 || inst >= int(h->inst.size()))
+        return fail(DG_EINVAL, "bad argument");
+    const HostMesh& m = h->inst[inst].mesh;
+    std::copy(m.etoe.begin(), m.etoe.end(), etoe);
+    std::copy(m.etof.begin(), m.etof.end(), etof);
+    return DG_OK;
+}
+
+int32_t dg_get_levels(const dg_solver* h, int32_t inst, int8_t* level, double* dt_min) {
+    if (!h || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    const HostMesh& m = h->inst[inst].mesh;
+    if (level) std::copy(m.level.begin(), m.level.end(), level);
+    if (dt_min) *dt_min = h->inst[inst].dt_min;
+    return DG_OK;
+}
+
+int32_t dg_get_tvb_stencil(const dg_solver* h, int32_t inst, int8_t* pair, double* alpha) {
+    if (!h || !pair || !alpha || inst < 0 || inst >= int(h->inst.size()))
+        return fail(DG_EINVAL, "bad argument");
+    const HostMesh& m = h->inst[inst].mesh;
+    std::copy(m.pair.begin(), m.pair.end(), pair);
+    std::copy(m.alpha.begin(), m.alpha.end(), alpha);
+    return DG_OK;
+}
+
+int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* stream) {
+    if (!h || !device_workspace) return fail(DG_EINVAL, "null handle or workspace");
+    if ((reinterpret_cast<uintptr_t>(device_workspace) & 255) != 0)
+        return fail(DG_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < int64_t(h->lay.total))
+        return fail(DG_ENOMEM, "workspace too small: need " + std::to_string(h->lay.total) + " bytes");
+    HIPCHECK(hipGetDevice(&h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    h->ws = static_cast<char*>(device_workspace);
+    const Layout& l = h->lay;
+    const RefElement& re = h->re;
+    const int Np = h->Np, nF = h->nF;
+    std::vector<float> Dr(Np * Np), Ds(Np * Np), LIFT(Np * nF);
+    for (int t = 0; t < Np * Np; ++t) { Dr[t] = float(re.Dr.a[t]); Ds[t] = float(re.Ds.a[t]); }
+    for (int t = 0; t < Np * nF; ++t) LIFT[t] = float(re.LIFT.a[t]);
+    std::vector<int> nodeface(2 * Np, -1);
+    for (int f = 0; f < 3; ++f)
+        for (int j = 0; j < h->Nfp; ++j) {
+            const int n = re.fmask[f * h->Nfp + j];
+            if (nodeface[2 * n] < 0) nodeface[2 * n] = f * h->Nfp + j;
+            else nodeface[2 * n + 1] = f * h->Nfp + j;
+        }
+    std::vector<double> wh(Np), pmid(3 * Np), phi(3 * Np);
+    for (int j = 0; j < Np; ++j) wh[j] = 0.5 * re.w[j];
+    for (int e = 0; e < 3; ++e)
+        for (int j = 0; j < Np; ++j) {
+            pmid[e * Np + j] = re.p1_mid(e, j) - 0.5 * re.w[j];
+            phi[e * Np + j] = re.phi_mid(e, j);
+        }
+    auto up = [&](size_t off, const void* src, size_t n) {
+        return hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIPCHECK(up(l.Dr, Dr.data(), Dr.size() * 4));
+    HIPCHECK(up(l.Ds, Ds.data(), Ds.size() * 4));
+    HIPCHECK(up(l.LIFT, LIFT.data(), LIFT.size() * 4));
+    HIPCHECK(up(l.fmask, re.fmask.data(), re.fmask.size() * 4));
+    HIPCHECK(up(l.nodeface, nodeface.data(), nodeface.size() * 4));
+    HIPCHECK(up(l.wh, wh.data(), wh.size() * 8));
+    HIPCHECK(up(l.pmid, pmid.data(), pmid.size() * 8));
+    HIPCHECK(up(l.phi, phi.data(), phi.size() * 8));
+    HIPCHECK(up(l.wfull, re.w.data(), re.w.size() * 8));
+    HIPCHECK(up(l.conn, h->conn.data(), h->conn.size() * 4));
+    HIPCHECK(up(l.stencil, h->stencil.data(), h->stencil.size() * 4));
+    HIPCHECK(hipMemsetAsync(h->ws + l.dyn_begin, 0, l.dyn_end - l.dyn_begin, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (!h->exec) HIPCHECK(hipStreamCreateWithFlags(&h->exec, hipStreamNonBlocking));
+    h->bound = true;
+    h->prepared = false;
+    return DG_OK;
+}
+
+int32_t dg_set_bathymetry(dg_solver* h, int32_t inst, const double* B) {
+    if (!h || !B || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    const int Np = h->Np;
+    Inst& I = h->inst[inst];
+    if (h->B64.empty()) h->B64.assign(size_t(h->K) * Np, 0.0);
+    if (h->Bh.empty()) h->Bh.assign(size_t(h->K) * Np, 0.f);
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const int s = h->inv[I.offset + k];
+        for (int j = 0; j < Np; ++j) {
+            const double b = B[size_t(k) * Np + j];
+            if (!std::isfinite(b)) return fail(DG_ENUMERIC, "non-finite bathymetry");
+            h->B64[size_t(s) * Np + j] = b;
+        }
+    }
+    I.has_state = false;
+    I.has_B = true;
+    h->prepared = false;
+    return DG_OK;
+}
+
+int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double* hu, const double* hv,
+                     void* stream) {
+    (void)stream;
+    if (!h || !hh || !hu || !hv || inst < 0 || inst >= int(h->inst.size()))
+        return fail(DG_EINVAL, "bad argument");
+    if (!h->bound) return fail(DG_ENOTBOUND, "dg_bind must be called before dg_set_state");
+    Inst& I = h->inst[inst];
+    if (!I.has_B) return fail(DG_ESTATE, "set the bathymetry of the instance first");
+    const int Np = h->Np;
+    const size_t KNp = size_t(h->K) * Np;
+    if (h->Qh.empty()) h->Qh.assign(3 * KNp, 0.f);
+    double amax = 0.0, eta_sum = 0.0;
+    long long n_wet = 0;
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const int s = h->inv[I.offset + k];
+        for (int j = 0; j < Np; ++j) {
+            const size_t src = size_t(k) * Np + j, dst = size_t(s) * Np + j;
+            const double d = hh[src], mu = hu[src], mv = hv[src];
+            if (!std::isfinite(d) || !std::isfinite(mu) || !std::isfinite(mv))
+                return fail(DG_ENUMERIC, "non-finite initial state");
+            if (d < 0.0) return fail(DG_ENUMERIC, "negative initial depth");
+            if (d > h->p.h0) {
+                eta_sum += d + h->B64[dst];
+                ++n_wet;
+            }
+            const double f = 2.0 * d / (d * d + std::fmax(d * d, h->p.hvel * h->p.hvel));
+            const double u = mu * f, v = mv * f;
+            amax = std::fmax(amax, std::sqrt(u * u + v * v) + std::sqrt(h->p.g * d));
+        }
+    }
+    // datum: mean wet surface level, rounded to FP32
+    I.datum = n_wet ? float(eta_sum / double(n_wet)) : 0.f;
+    const double datum = double(I.datum);
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const int s = h->inv[I.offset + k];
+        for (int j = 0; j < Np; ++j) {
+            const size_t src = size_t(k) * Np + j, dst = size_t(s) * Np + j;
+            const double b = h->B64[dst];
+            // eta = h + B is snapped to a 2^-40 grid so that FP64 noise of the
+            // caller's data (still water given as h = eta0 - B) does not reach
+            // the finely rounded eta - datum; a dry node stores its bed value
+            // and no node stores a surface below its bed
+            const float bs = float(b - datum);
+            float es = bs;
+            if (hh[src] > 0.0) {
+                const double eta = hh[src] + b;
+                const double snapped = std::fabs(eta) < 4096.0 ? std::nearbyint(eta * 0x1p40) * 0x1p-40 : eta;
+                es = std::fmax(float(snapped - datum), bs);
+            }
+            h->Bh[dst] = bs;
+            h->Qh[dst] = es;
+            h->Qh[KNp + dst] = float(hu[src]);
+            h->Qh[2 * KNp + dst] = float(hv[src]);
+        }
+    }
+    double rmin = I.mesh.inradius[0];
+    for (double r : I.mesh.inradius) rmin = std::fmin(rmin, r);
+    I.a_max = amax;
+    I.dt_min = h->p.cfl * rmin / (double((h->p.N + 1) * (h->p.N + 1)) * std::fmax(amax, 1e-12));
+    I.time = 0.0;
+    I.has_state = true;
+    h->prepared = false;
+    return DG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// stepping helpers
+// ---------------------------------------------------------------------------
+static StepArgs base_step_args(dg_solver* h) {
+    StepArgs a{};
+    const Layout& l = h->lay;
+    a.N = h->p.N;
+    a.engine = engine_of(h->p.precision);
+    a.K = h->K;
+    a.KNp = (long long)h->K * h->Np;
+    a.KnF = (long long)h->K * h->nF;
+    a.nlev = h->L;
+    for (int q = 0; q < 2; ++q) a.Q[q] = reinterpret_cast<float*>(h->ws + l.Q[q]);
+    a.B = reinterpret_cast<const float*>(h->ws + l.B);
+    for (int s = 0; s < 3; ++s) a.R[s] = reinterpret_cast<float*>(h->ws + l.R[s]);
+    a.half = h->L > 1 ? reinterpret_cast<float*>(h->ws + l.half) : nullptr;
+    a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
+    a.conn = reinterpret_cast<const int*>(h->ws + l.conn);
+    a.means = reinterpret_cast<double*>(h->ws + l.means);
+    a.devs = reinterpret_cast<float*>(h->ws + l.devs);
+    a.flags = reinterpret_cast<uint8_t*>(h->ws + l.flags);
+    a.counters = reinterpret_cast<unsigned long long*>(h->ws + l.counters);
+    a.ops.Dr = reinterpret_cast<const float*>(h->ws + l.Dr);
+    a.ops.Ds = reinterpret_cast<const float*>(h->ws + l.Ds);
+    a.ops.LIFT = reinterpret_cast<const float*>(h->ws + l.LIFT);
+    a.ops.Amfma = reinterpret_cast<const float*>(h->ws + l.Amfma);
+    a.ops.fmask = reinterpret_cast<const int*>(h->ws + l.fmask);
+    a.ops.nodeface = reinterpret_cast<const int*>(h->ws + l.nodeface);
+    a.ops.wh = reinterpret_cast<const double*>(h->ws + l.wh);
+    a.ops.pmid = reinterpret_cast<const double*>(h->ws + l.pmid);
+    a.ops.phi = reinterpret_cast<const double*>(h->ws + l.phi);
+    a.g = float(h->p.g);
+    a.h0 = float(h->p.h0);
+    a.eps = float(h->p.eps);
+    a.hvel = float(h->p.hvel);
+    a.pp_on = (h->p.limiter_mask & DG_LIMIT_PP) ? 1 : 0;
+    a.dry_literal = h->p.dry_literal;
+    return a;
+}
+
+static void fill_levels(dg_solver* h, LevelArgs* lev, int n_active, bool limit_only) {
+    for (int l = 0; l < h->L; ++l) {
+        LevelArgs& la = lev[l];
+        la = LevelArgs{};
+        la.begin = h->lev_begin[l];
+        la.end = h->lev_end[l];
+        la.parity = h->parity[l];
+        la.active = (l < n_active) ? 1 : 0;
+        la.scale = float(1 << l);
+        const int nh = std::min(h->nhist[l], 2);
+        for (int c = 0; c < 3; ++c) {
+            la.ab[c] = limit_only ? 0.f : kAB[nh][c];
+            la.half[c] = kHalf[nh][c];
+        }
+        la.slot[0] = h->head[l];
+        la.slot[1] = (h->head[l] + 2) % 3;
+        la.slot[2] = (h->head[l] + 1) % 3;
+        la.write_half = (l > 0 && h->L > 1) ? 1 : 0;
+    }
+}
+
+static TvbArgs tvb_args(dg_solver* h, const StepArgs& sa) {
+    TvbArgs t{};
+    t.K = h->K;
+    t.KNp = sa.KNp;
+    t.Np = h->Np;
+    t.nlev = h->L;
+    for (int l = 0; l < kMaxLevels; ++l) t.lev[l] = sa.lev[l];
+    t.Q[0] = sa.Q[0];
+    t.Q[1] = sa.Q[1];
+    t.B = sa.B;
+    t.geo = sa.geo;
+    t.conn = sa.conn;
+    t.stencil = reinterpret_cast<const float*>(h->ws + h->lay.stencil);
+    t.means = sa.means;
+    t.devs = sa.devs;
+    t.flags = sa.flags;
+    t.phi = sa.ops.phi;
+    t.g = h->p.g;
+    t.h0 = h->p.h0;
+    t.nu = h->p.tvb_nu;
+    return t;
+}
+
+// Enqueue one tick (single rate: one step) on stream s.
+static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) {
+    int m = 1;
+    if (!limit_only)
+        while (m < h->L && tick % (1 << m) == 0) ++m;
+    else
+        m = h->L;
+    StepArgs a = base_step_args(h);
+    fill_levels(h, a.lev, m, limit_only);
+    a.k_begin = 0;
+    a.k_end = h->lev_end[m - 1];
+    const bool prof = h->profiling && !limit_only;
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (prof) {
+        if (h->prof_used == h->prof_events.size()) {
+            hipEvent_t e0, e1;
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            h->prof_events.push_back({e0, e1});
+        }
+        ev = &h->prof_events[h->prof_used++];
+    }
+    if (limit_only) {
+        a.mode = MODE_LIMIT_ONLY;
+        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+    } else if (h->p.precision == DG_PLAIN_FP32) {
+        a.mode = MODE_RHS_ONLY;
+        if (prof) HIPCHECK(hipEventRecord(ev->first, s));
+        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+        if (prof) HIPCHECK(hipEventRecord(ev->second, s));
+        a.mode = MODE_UPDATE_ONLY;
+        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+    } else {
+        a.mode = MODE_FUSED;
+        if (prof) HIPCHECK(hipEventRecord(ev->first, s));
+        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+        if (prof) HIPCHECK(hipEventRecord(ev->second, s));
+    }
+    if (h->p.limiter_mask & DG_LIMIT_TVB) {
+        TvbArgs t = tvb_args(h, a);
+        t.k_begin = 0;
+        t.k_end = a.k_end;
+        if (launch_tvb(t, s)) return fail(DG_EDEVICE, device_error_string());
+    }
+    for (int l = 0; l < m; ++l) {
+        h->parity[l] ^= 1;
+        if (!limit_only) {
+            h->head[l] = (h->head[l] + 1) % 3;
+            h->nhist[l] = std::min(h->nhist[l] + 1, 2);
+        }
+    }
+    if (!limit_only)
+        for (size_t i = 0; i < h->inst.size(); ++i) h->inst[i].time += h->inst[i].dt_min;
+    return DG_OK;
+}
+
+static int enqueue_coarse_step(dg_solver* h, hipStream_t s) {
+    const int ticks = 1 << (h->L - 1);
+    for (int t = 0; t < ticks; ++t) {
+        const int rc = enqueue_tick(h, t, s, false);
+        if (rc) return rc;
+    }
+    h->steps += 1;
+    return DG_OK;
+}
+
+static void state_key(const dg_solver* h, int* key) {
+    for (int l = 0; l < kMaxLevels; ++l) {
+        key[3 * l] = h->parity[l];
+        key[3 * l + 1] = h->head[l];
+        key[3 * l + 2] = h->nhist[l];
+    }
+}
+
+static bool all_started(const dg_solver* h) {
+    for (int l = 0; l < h->L; ++l)
+        if (h->nhist[l] < 2) return false;
+    return true;
+}
+
+extern "C" {
+
+int32_t dg_prepare(dg_solver* h, void* stream) {
+    if (!h) return fail(DG_EINVAL, "null handle");
+    if (!h->bound) return fail(DG_ENOTBOUND, "no device buffer bound");
+    for (size_t i = 0; i < h->inst.size(); ++i)
+        if (!h->inst[i].has_state || !h->inst[i].has_B)
+            return fail(DG_ENOTBOUND, "instance " + std::to_string(i) + " has no state/bathymetry");
+    HIPCHECK(hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout& l = h->lay;
+    for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
+    HIPCHECK(hipMemcpyAsync(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemsetAsync(h->ws + l.dyn_begin, 0, l.dyn_end - l.dyn_begin, s));
+    for (int q = 0; q < kMaxLevels; ++q) {
+        h->parity[q] = 0;
+        h->head[q] = 0;
+        h->nhist[q] = 0;
+    }
+    HIPCHECK(hipMemcpyAsync(h->ws + l.Q[0], h->Qh.data(), h->Qh.size() * 4, hipMemcpyHostToDevice, s));
+    h->steps = 0;
+    for (auto& I : h->inst) I.time = 0.0;
+    // Q0 = TVB(PP(Pi_H Q0)), first line of Algorithm 5.1
+    const int rc = enqueue_tick(h, 0, s, true);
+    if (rc) return rc;
+    HIPCHECK(hipStreamSynchronize(s));
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+        h->have_graph = false;
+    }
+    h->prepared = true;
+    return DG_OK;
+}
+
+int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
+    if (!h) return fail(DG_EINVAL, "null handle");
+    if (n_steps < 0) return fail(DG_EINVAL, "n_steps < 0");
+    if (!h->prepared) {
+        const int rc = dg_prepare(h, stream);
+        if (rc) return rc;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int period = 6;   // ring (3) and ping-pong (2) state repeats every 6 steps
+    while (n_steps > 0) {
+        const bool graph_ok = h->p.use_graph && !h->profiling && all_started(h) && n_steps >= period;
+        if (graph_ok) {
+            int key[3 * kMaxLevels];
+            state_key(h, key);
+            if (h->have_graph && std::memcmp(key, h->graph_key, sizeof(key)) != 0) {
+                // state not aligned with the captured sequence: one eager step
+                const int rc = enqueue_coarse_step(h, s);
+                if (rc) return rc;
+                --n_steps;
+                continue;
+            }
+            if (!h->have_graph) {
+                std::memcpy(h->graph_key, key, sizeof(key));
+                hipGraph_t g;
+                HIPCHECK(hipStreamBeginCapture(h->exec, hipStreamCaptureModeThreadLocal));
+                int rc = DG_OK;
+                for (int q = 0; q < period && rc == DG_OK; ++q) rc = enqueue_coarse_step(h, h->exec);
+                hipGraph_t gout;
+                const hipError_t ce = hipStreamEndCapture(h->exec, &gout);
+                if (rc) return rc;
+                if (ce != hipSuccess) return fail(DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+                g = gout;
+                HIPCHECK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
+                (void)hipGraphDestroy(g);
+                h->have_graph = true;
+                // capture advanced the host-side counters; undo them, the launch below replays
+                h->steps -= period;
+                for (auto& I : h->inst) I.time -= period * (1 << (h->L - 1)) * I.dt_min;
+            }
+            hipEvent_t e0, e1;
+            HIPCHECK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+            HIPCHECK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+            HIPCHECK(hipEventRecord(e0, s));
+            HIPCHECK(hipStreamWaitEvent(h->exec, e0, 0));
+            while (n_steps >= period) {
+                HIPCHECK(hipGraphLaunch(h->graph, h->exec));
+                n_steps -= period;
+                h->steps += period;
+                for (auto& I : h->inst) I.time += period * (1 << (h->L - 1)) * I.dt_min;
+            }
+            HIPCHECK(hipEventRecord(e1, h->exec));
+            HIPCHECK(hipStreamWaitEvent(s, e1, 0));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            continue;
+        }
+        const int rc = enqueue_coarse_step(h, s);
+        if (rc) return rc;
+        --n_steps;
+    }
+    return DG_OK;
+}
+
+int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double* hv, void* stream) {
+    if (!h || !hh || !hu || !hv || inst < 0 || inst >= int(h->inst.size()))
+        return fail(DG_EINVAL, "bad argument");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHECK(hipStreamSynchronize(s));
+    const int Np = h->Np;
+    const size_t KNp = size_t(h->K) * Np;
+    const Inst& I = h->inst[inst];
+    std::vector<float> q(3 * KNp), b(KNp);
+    for (int l = 0; l < h->L; ++l) {
+        const size_t b0 = size_t(h->lev_begin[l]) * Np, n = size_t(h->lev_end[l] - h->lev_begin[l]) * Np;
+        if (!n) continue;
+        for (int c = 0; c < 3; ++c)
+            HIPCHECK(hipMemcpy(q.data() + c * KNp + b0, h->ws + h->lay.Q[h->parity[l]] + (c * KNp + b0) * 4,
+                               n * 4, hipMemcpyDeviceToHost));
+    }
+    HIPCHECK(hipMemcpy(b.data(), h->ws + h->lay.B, KNp * 4, hipMemcpyDeviceToHost));
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const size_t sidx = size_t(h->inv[I.offset + k]);
+        for (int j = 0; j < Np; ++j) {
+            const size_t src = sidx * Np + j, dst = size_t(k) * Np + j;
+            hh[dst] = double(q[src]) - double(b[src]);
+            hu[dst] = double(q[KNp + src]);
+            hv[dst] = double(q[2 * KNp + src]);
+        }
+    }
+    return DG_OK;
+}
+
+int32_t dg_get_flags(dg_solver* h, int32_t inst, uint8_t* flags, void* stream) {
+    if (!h || !flags || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
+    HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    std::vector<uint8_t> f(h->K);
+    HIPCHECK(hipMemcpy(f.data(), h->ws + h->lay.flags, h->K, hipMemcpyDeviceToHost));
+    const Inst& I = h->inst[inst];
+    for (int k = 0; k < I.mesh.K; ++k) flags[k] = f[h->inv[I.offset + k]];
+    return DG_OK;
+}
+
+int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream) {
+    if (!h || !d || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DiagArgs a{};
+    const Layout& l = h->lay;
+    a.K = h->K;
+    a.Np = h->Np;
+    a.k_begin = 0;
+    a.k_end = h->K;
+    a.inst = inst;
+    a.KNp = (long long)h->K * h->Np;
+    a.Q = reinterpret_cast<const float*>(h->ws + l.Q[0]);
+    a.Q2 = reinterpret_cast<const float*>(h->ws + l.Q[1]);
+    a.nlev = h->L;
+    fill_levels(h, a.lev, h->L, true);
+    a.B = reinterpret_cast<const float*>(h->ws + l.B);
+    a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
+    a.wfull = reinterpret_cast<const double*>(h->ws + l.wfull);
+    a.flags = reinterpret_cast<const uint8_t*>(h->ws + l.flags);
+    a.partial = reinterpret_cast<double*>(h->ws + l.diag_partial);
+    a.out = reinterpret_cast<double*>(h->ws + l.diag_out);
+    if (launch_diag(a, s)) return fail(DG_EDEVICE, device_error_string());
+    double out[16];
+    unsigned long long cnt[8];
+    HIPCHECK(hipStreamSynchronize(s));
+    HIPCHECK(hipMemcpy(out, h->ws + l.diag_out, 9 * 8, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(cnt, h->ws + l.counters, 8, hipMemcpyDeviceToHost));
+    d->mass = out[0];
+    d->min_depth = out[1];
+    d->time = h->inst[inst].time;
+    d->steps = h->steps;
+    d->negative_means = (int64_t)cnt[0];
+    for (int q = 0; q < 3; ++q) d->pp_counts[q] = (int64_t)out[2 + q];
+    for (int q = 0; q < 4; ++q) d->tvb_counts[q] = (int64_t)out[5 + q];
+    return DG_OK;
+}
+
+int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes) {
+    if (!h || !bytes) return fail(DG_EINVAL, "bad argument");
+    *bytes = int64_t(256 + (h->lay.dyn_end - h->lay.dyn_begin));
+    return DG_OK;
+}
+
+struct CkptHeader {
+    uint64_t magic, K, Np, L;
+    int32_t parity[kMaxLevels], head[kMaxLevels], nhist[kMaxLevels];
+    int64_t steps;
+};
+
+int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream) {
+    int64_t need = 0;
+    if (dg_checkpoint_bytes(h, &need)) return DG_EINVAL;
+    if (!blob || bytes < need) return fail(DG_EINVAL, "checkpoint buffer too small");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
+    if (h->inst.size() > 8) return fail(DG_EINVAL, "checkpoints support at most 8 instances");
+    HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    char* b = static_cast<char*>(blob);
+    std::memset(b, 0, 256);
+    CkptHeader* hd = reinterpret_cast<CkptHeader*>(b);
+    hd->magic = 0x44475357u;
+    hd->K = h->K;
+    hd->Np = h->Np;
+    hd->L = h->L;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        hd->parity[l] = h->parity[l];
+        hd->head[l] = h->head[l];
+        hd->nhist[l] = h->nhist[l];
+    }
+    hd->steps = h->steps;
+    double* times = reinterpret_cast<double*>(b + 128);
+    for (size_t i = 0; i < h->inst.size(); ++i) times[i] = h->inst[i].time;
+    HIPCHECK(hipMemcpy(b + 256, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
+                       hipMemcpyDeviceToHost));
+    return DG_OK;
+}
+
+int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* stream) {
+    int64_t need = 0;
+    if (dg_checkpoint_bytes(h, &need)) return DG_EINVAL;
+    if (!blob || bytes < need) return fail(DG_EINVAL, "checkpoint buffer too small");
+    if (!h->prepared) return fail(DG_ESTATE, "call dg_prepare (or advance) before restoring");
+    const char* b = static_cast<const char*>(blob);
+    const CkptHeader* hd = reinterpret_cast<const CkptHeader*>(b);
+    if (hd->magic != 0x44475357u || hd->K != uint64_t(h->K) || hd->Np != uint64_t(h->Np) ||
+        hd->L != uint64_t(h->L))
+        return fail(DG_EINVAL, "checkpoint does not match this solver");
+    HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + 256, h->lay.dyn_end - h->lay.dyn_begin,
+                       hipMemcpyHostToDevice));
+    for (int l = 0; l < kMaxLevels; ++l) {
+        h->parity[l] = hd->parity[l];
+        h->head[l] = hd->head[l];
+        h->nhist[l] = hd->nhist[l];
+    }
+    h->steps = hd->steps;
+    const double* times = reinterpret_cast<const double*>(b + 128);
+    for (size_t i = 0; i < h->inst.size(); ++i) h->inst[i].time = times[i];
+    return DG_OK;
+}
+
+int32_t dg_set_profiling(dg_solver* h, int32_t on) {
+    if (!h) return fail(DG_EINVAL, "null handle");
+    h->profiling = on != 0;
+    h->prof_used = 0;
+    return DG_OK;
+}
+
+int32_t dg_kernel_timing(const dg_solver* hc, double* avg_us, int64_t* launches, int64_t* elems) {
+    if (!hc) return fail(DG_EINVAL, "null handle");
+    dg_solver* h = const_cast<dg_solver*>(hc);
+    double tot = 0.0;
+    for (size_t i = 0; i < h->prof_used; ++i) {
+        HIPCHECK(hipEventSynchronize(h->prof_events[i].second));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, h->prof_events[i].first, h->prof_events[i].second));
+        tot += ms;
+    }
+    if (avg_us) *avg_us = h->prof_used ? tot * 1000.0 / h->prof_used : 0.0;
+    if (launches) *launches = (int64_t)h->prof_used;
+    if (elems) *elems = h->K;
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Kernel argument blocks and launchers shared by the host solver and the HIP
+// kernels.  Plain C++ types only; streams travel as void*.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dgswe {
+
+constexpr int kMaxLevels = 6;
+
+// Kernel modes of the step kernel.
+enum StepMode : int {
+    MODE_FUSED = 0,        // RHS + AB update + positivity limiter + means/deviations
+    MODE_RHS_ONLY = 1,     // RHS into ring slot 0 (unfused path, first kernel)
+    MODE_UPDATE_ONLY = 2,  // AB update from ring slots + limiter (unfused path, second kernel)
+    MODE_LIMIT_ONLY = 3,   // copy state + positivity limiter (initial Q0 = TVB(PP(Q0)))
+};
+
+// Contraction engine of the step kernel.
+enum Engine : int { ENGINE_VALU = 0, ENGINE_MFMA_F32 = 1, ENGINE_MFMA_BF16X3 = 2 };
+
+struct LevelArgs {
+    int begin, end;        // element range of the level (sorted order)
+    int parity;            // ping-pong buffer holding the level's current state
+    int active;            // level steps at this tick
+    float scale;           // dt_l / dt_min = 2^(l-1)
+    float ab[3];           // Adams-Bashforth weights (zeros beyond the history)
+    int slot[3];           // ring slots of R^n, R^{n-1}, R^{n-2}
+    float half[3];         // half-step weights when write_half
+    int write_half;        // level writes its half-step face traces
+};
+
+struct DevOps {
+    const float* Dr;       // Np x Np
+    const float* Ds;       // Np x Np
+    const float* LIFT;     // Np x 3Nfp
+    const float* Amfma;    // MFMA operator tiles (engine dependent) or null
+    const int* fmask;      // 3Nfp
+    const int* nodeface;   // Np x 2 (face-node slot of each volume node, -1 none)
+    const double* wh;      // Np: w / 2 (cell-mean weights)
+    const double* pmid;    // 3 x Np: P1 midpoint value minus mean
+    const double* phi;     // 3 x Np: midpoint-Lagrange P1 basis at the nodes
+};
+
+struct StepArgs {
+    int N, mode, engine;
+    int K;                 // total elements
+    long long KNp;         // K * Np (field stride)
+    long long KnF;         // K * 3Nfp (half-trace field stride)
+    int k_begin, k_end;    // element range of this launch
+    int nlev;
+    LevelArgs lev[kMaxLevels];
+    float* Q[2];           // ping-pong state buffers [3][K*Np]: eta, hu, hv
+    const float* B;        // [K*Np]
+    float* R[3];           // ring slots [3][K*Np]
+    float* half;           // [3][K*3Nfp] half-step face traces (multi-rate) or null
+    const float* geo;      // [K][16]
+    const int* conn;       // [K][4]
+    double* means;         // [3][K]
+    float* devs;           // [9][K]
+    uint8_t* flags;        // [K]
+    unsigned long long* counters;  // [0] negative-mean events
+    DevOps ops;
+    float g, h0, eps, hvel;
+    int pp_on, dry_literal;
+};
+
+struct TvbArgs {
+    int K;
+    long long KNp;
+    int Np;
+    int k_begin, k_end;
+    int nlev;
+    LevelArgs lev[kMaxLevels];
+    float* Q[2];
+    const float* B;
+    const float* geo;
+    const int* conn;
+    const float* stencil;  // [K][16]
+    const double* means;
+    const float* devs;
+    uint8_t* flags;
+    const double* phi;     // 3 x Np
+    double g, h0, nu;
+};
+
+struct DiagArgs {
+    int K, Np, k_begin, k_end, inst;
+    long long KNp;
+    const float* Q;        // state buffer [3][K*Np] (per element parity resolved by caller)
+    const float* Q2;       // second buffer
+    const int* parity_of;  // null: all from Q; else per-level parity via lev table
+    int nlev;
+    LevelArgs lev[kMaxLevels];
+    const float* B;
+    const float* geo;
+    const double* wfull;   // Np: w
+    const uint8_t* flags;
+    double* partial;       // [blocks][16]
+    double* out;           // [16]
+};
+
+int launch_step(const StepArgs& a, void* stream, int elems_per_block);
+int launch_tvb(const TvbArgs& a, void* stream);
+int launch_diag(const DiagArgs& a, void* stream);
+int step_elems_per_block(int N, int engine);
+const char* device_error_string();
+
+}  // namespace dgswe
