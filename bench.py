@@ -1,0 +1,185 @@
+"""Throughput of the DG shallow-water hot path on one MI355X.
+
+One step = one single-rate AB3 step of the whole path: right-hand side
+(volume + well-balanced LLF surface term + lift), AB update, positivity
+limiter, TVB limiter.  Workload: 256x256x2 jittered triangles on the unit
+square (131072 elements), N = 4 (15 nodes), sloping beach with eight bumps,
+still level 0.5, Gaussian hump, wet/dry, CFL 0.2; inputs are resident in HBM
+before the timed region.
+
+Prints one JSON line: node-updates/s (value), the roofline of the fused step
+kernel (algorithmic bytes over its HIP-event time, against 8 TB/s), the
+plain (unfused) FP32 path on the same GPU, relative L2 against the FP64
+oracle after the configured 500 steps (when the stored oracle samples are
+present), and the oracle's own throughput on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_oracle_samples.npz")
+
+
+def step_kernel_bytes(Np: int) -> int:
+    """Algorithmic HBM bytes per element of one fused step-kernel launch:
+    state read+write 2*3*Np*4, bed Np*4, RHS ring 1 write + 2 reads 3*3*Np*4,
+    geometry 64, connectivity 16, FP64 means 24, midpoint deviations 36,
+    flag 1.  Neighbour face values (halo) are not counted."""
+    return 64 * Np + 141
+
+
+def make_solver(wl, precision, use_graph=1):
+    from paper_1403_1661_amd import dgswe
+    ins = wl.instances[0]
+    s = dgswe.Solver([(ins.vx, ins.vy, ins.etov)], wl.N, g=wl.g, cfl=wl.cfl,
+                     precision=precision, use_graph=use_graph)
+    s.bind("cuda:0")
+    x, y = s.node_coords(0)
+    s.set_bathymetry(0, ins.bathymetry(x, y))
+    s.set_state(0, *ins.initial(x, y))
+    s.prepare()
+    return s
+
+
+def timed(s, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The FP64 oracle on this host: steps of the same workload until about
+    budget_s of CPU work, BLAS pinned to one thread."""
+    from threadpoolctl import threadpool_limits
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import oracle_solver
+    with threadpool_limits(limits=1):
+        o = oracle_solver(wl)
+        o.step()
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            o.step()
+            n += 1
+        dt = time.perf_counter() - t0
+    nodes = o.K * o.ref.Np
+    return {"value": nodes * n / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} AB3 steps (after one warm step) of the same 131072-element N=4 "
+                      f"workload, {dt:.1f} s, NumPy FP64, BLAS on 1 thread"}
+
+
+def rel_l2_vs_golden(s, wl):
+    if not os.path.exists(GOLDEN):
+        return None
+    z = np.load(GOLDEN)
+    idx = z["elements"]
+    h, hu, hv = s.get_state(0)
+    M, J = z["mass_matrix"], z["J"]
+    out = {}
+    for name, test, ref in (("h", [h[idx]], [z["h"]]), ("m", [hu[idx], hv[idx]], [z["hu"], z["hv"]])):
+        num = sum(float(np.sum(J * np.einsum("ki,ij,kj->k", a - b, M, a - b))) for a, b in zip(test, ref))
+        den = sum(float(np.sum(J * np.einsum("ki,ij,kj->k", b, M, b))) for b in ref)
+        out[name] = float(np.sqrt(num / den))
+    out["elements_sampled"] = int(idx.size)
+    out["steps"] = int(z["steps"])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=480)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fused_fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is measured "
+              "on one GPU's share and its multi-GPU sharding is a design note", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    assert torch.cuda.is_available(), "needs a GPU"
+    wl = W.c2()
+    K = wl.n_elements
+    Np = wl.Np
+
+    s = make_solver(wl, args.precision)
+    s.advance(args.warmup)
+    torch.cuda.synchronize()
+    t = timed(s, args.steps, torch)
+    ms = 1e3 * t / args.steps
+    value = K * Np * args.steps / t
+    accuracy = None
+    if args.warmup + args.steps == wl.steps:
+        accuracy = rel_l2_vs_golden(s, wl)
+    diag = s.diagnostics(0)
+
+    # per-launch duration of the fused step kernel: HIP events recorded on the
+    # stream it runs on, over a second region of the same length
+    s.set_profiling(True)
+    s.advance(args.steps)
+    torch.cuda.synchronize()
+    avg_us, launches, elems = s.kernel_timing()
+    s.set_profiling(False)
+    bytes_launch = step_kernel_bytes(Np) * elems
+    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+
+    plain = None
+    if not args.no_plain and args.precision != "plain_fp32":
+        p = make_solver(wl, "plain_fp32")
+        p.advance(args.warmup)
+        tp = timed(p, args.steps, torch)
+        plain = {"value": K * Np * args.steps / tp, "ms_per_step": 1e3 * tp / args.steps}
+        del p
+
+    out = {
+        "metric": "DG node-updates/s + HBM GB/s; FP32/BF16-split vs FP32 plain at rel-L2 1e-5",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256x256x2 jittered triangles (131072) on [0,1]^2, N=4 (Np=15), "
+                               "beach 0.8x + 8 bumps, still level 0.5, hump 0.05, wet/dry PP+TVB, "
+                               "single-rate AB3 at CFL 0.2, 500 configured steps",
+                   "elements": K, "N": wl.N, "path": args.precision, "parallelism": "single GPU"},
+        "hbm_gbps_algorithmic_step": step_kernel_bytes(Np) * K * args.steps / t / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step_kernel<4> (fused RHS + AB3 + positivity)",
+                     "kernel_avg_us": avg_us, "launches_timed": launches,
+                     "bytes_per_launch": bytes_launch},
+        "plain_fp32": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "rel_l2_vs_oracle": accuracy,
+        "diagnostics": {"mass": diag["mass"], "min_depth": diag["min_depth"],
+                        "pp_counts": diag["pp_counts"], "tvb_counts": diag["tvb_counts"],
+                        "negative_means": diag["negative_means"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

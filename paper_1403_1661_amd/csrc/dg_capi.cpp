@@ -178,8 +178,10 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         return fail(DG_EINVAL, "max_levels must be in 1..6");
     if (p->precision < DG_PLAIN_FP32 || p->precision > DG_FUSED_BF16X3)
         return fail(DG_EINVAL, "unknown precision/path");
-    if (p->precision == DG_FUSED_MFMA32 || p->precision == DG_FUSED_BF16X3)
-        return fail(DG_EINVAL, "MFMA contraction paths are not available in this build");
+    if (p->precision == DG_FUSED_BF16X3)
+        return fail(DG_EINVAL, "the BF16 split contraction is not available in this build");
+    if (p->precision == DG_FUSED_MFMA32 && p->N > 4)
+        return fail(DG_EINVAL, "the MFMA contraction needs Np <= 16 (N <= 4)");
     std::unique_ptr<dg_solver> h;
     try {
         h.reset(new dg_solver());
@@ -398,12 +400,30 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
             pmid[e * Np + j] = re.p1_mid(e, j) - 0.5 * re.w[j];
             phi[e * Np + j] = re.phi_mid(e, j);
         }
+    // MFMA B-operand of [Dr Ds LIFT]^T in lane order: step s, lane l holds
+    // Op[node l % 16][K index 4 s + l / 16] (0 outside Np x (2Np + 3Nfp))
+    std::vector<float> amfma;
+    if (h->p.N <= 4) {
+        const int KT = 2 * Np + nF, KS = mfma_steps(h->p.N);
+        amfma.assign(size_t(KS) * 64, 0.f);
+        for (int st = 0; st < KS; ++st)
+            for (int ln = 0; ln < 64; ++ln) {
+                const int node = ln % 16, kk = 4 * st + ln / 16;
+                if (node >= Np || kk >= KT) continue;
+                double v;
+                if (kk < Np) v = re.Dr(node, kk);
+                else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
+                else v = re.LIFT(node, kk - 2 * Np);
+                amfma[size_t(st) * 64 + ln] = float(v);
+            }
+    }
     auto up = [&](size_t off, const void* src, size_t n) {
         return hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, s);
     };
     HIPCHECK(up(l.Dr, Dr.data(), Dr.size() * 4));
     HIPCHECK(up(l.Ds, Ds.data(), Ds.size() * 4));
     HIPCHECK(up(l.LIFT, LIFT.data(), LIFT.size() * 4));
+    if (!amfma.empty()) HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
     HIPCHECK(up(l.fmask, re.fmask.data(), re.fmask.size() * 4));
     HIPCHECK(up(l.nodeface, nodeface.data(), nodeface.size() * 4));
     HIPCHECK(up(l.wh, wh.data(), wh.size() * 8));

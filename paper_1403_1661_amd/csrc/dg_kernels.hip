@@ -17,7 +17,7 @@
 //      reflective wall ghost; hydrostatic reconstruction h* (Eq. 5.1) and the
 //      well-balanced Lax-Friedrichs flux (Eq. 5.2) with the wave speed maxed
 //      over the face; the (g/2) h^2 terms of F(Q-).n and of the pressure
-//      correction cancel symbolically;
+//      correction cancel symbolically and the rest is formed from h*- - h*+;
 //   4. R = -Dr X_r - Ds X_s + LIFT (Fscale dF) + S (Section 3, Eq. 3.3);
 //   5. Adams-Bashforth update with the level's weights (Algorithm 4.1), RHS
 //      written to the ring, half-step face traces for finer neighbours;
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ float sDr[Np * Np], sDs[Np * Np], sL[Np * nF];
     __shared__ int sFm[nF];
     __shared__ float sQ[4][E * Np];       // eta, hu, hv, B
-    __shared__ float sX[6][E * Np];       // X_r (3 fields), X_s (3 fields)
+    __shared__ float sX[7][E * Np];       // X_r (3 fields), X_s (3 fields), B - B_k
     __shared__ float sT[4][E * nF];       // exterior eta, hu, hv, B
     __shared__ float sLam[E * nF];
     __shared__ float sF[3][E * nF];
@@ -141,6 +141,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         if (live) {
             const float h = eta - Bn;
             dlt = eta - sQ[0][e * Np];
+            // bed relative to the element's first node: the gradient of B is
+            // taken from O(H |grad B|) values instead of O(|B|) ones
+            sX[6][tid] = Bn - sQ[3][e * Np];
             const float fv = vel_factor(h, hvel);
             const float u = hu * fv;
             const float v = hv * fv;
@@ -237,17 +240,17 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             const float Bmax = fmaxf(BM, BP);
             const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
             const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
-            const float pM = 0.5f * g * hsM * hsM, pP = 0.5f * g * hsP * hsP;
-            // Lax-Friedrichs flux of the reconstructed states
-            const float lfh = 0.5f * (hsM * unM + hsP * unP) - 0.5f * lam * (hsP - hsM);
-            const float lfu = 0.5f * ((hsM * uM * unM + pM * nx) + (hsP * uP * unP + pP * nx)) -
-                              0.5f * lam * (hsP * uP - hsM * uM);
-            const float lfv = 0.5f * ((hsM * vM * unM + pM * ny) + (hsP * vP * unP + pP * ny)) -
-                              0.5f * lam * (hsP * vP - hsM * vM);
-            // F(Q-).n - F*.n with the (g/2)(h-)^2 terms cancelled
-            sF[0][t] = fs * ((huM * nx + hvM * ny) - lfh);
-            sF[1][t] = fs * ((huM * uM * nx + huM * vM * ny) + pM * nx - lfu);
-            sF[2][t] = fs * ((hvM * uM * nx + hvM * vM * ny) + pM * ny - lfv);
+            // F(Q-).n - F*.n.  The (g/2)(h-)^2 of F(Q-).n cancels the one in the
+            // pressure correction of Eq. 5.2, and the remaining (g/2) h*^2 terms
+            // combine into (g/4)(h*- - h*+)(h*- + h*+): no O(1) quantities are
+            // subtracted, and the difference is exactly zero for still water.
+            const float dp = 0.25f * g * (hsM - hsP) * (hsM + hsP);
+            const float ah = hsM * unM + hsP * unP;
+            const float au = hsM * uM * unM + hsP * uP * unP;
+            const float av = hsM * vM * unM + hsP * vP * unP;
+            sF[0][t] = fs * ((huM * nx + hvM * ny) - 0.5f * ah + 0.5f * lam * (hsP - hsM));
+            sF[1][t] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
+            sF[2][t] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
         }
         __syncthreads();
         // ---- R = -(Dr X_r + Ds X_s) + LIFT dF + source
@@ -260,8 +263,8 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 a0 += dr * sX[0][b] + ds * sX[3][b];
                 a1 += dr * sX[1][b] + ds * sX[4][b];
                 a2 += dr * sX[2][b] + ds * sX[5][b];
-                br += dr * sQ[3][b];
-                bs += ds * sQ[3][b];
+                br += dr * sX[6][b];
+                bs += ds * sX[6][b];
             }
             float l0 = 0.f, l1 = 0.f, l2 = 0.f;
 #pragma unroll
@@ -412,6 +415,315 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             double val = sRed[e][1 + c];
 #pragma unroll
             for (int ed = 0; ed < 3; ++ed) val += th * sRed[e][4 + 3 * c + ed] * a.ops.phi[ed * Np + i];
+            out[c] = c == 0 ? (float)(val + (double)Bn) : (float)val;
+        }
+    }
+    float* Qo = a.Q[1 - L.parity];
+    Qo[idx] = out[0];
+    Qo[KNp + idx] = out[1];
+    Qo[2 * KNp + idx] = out[2];
+}
+
+// ---------------------------------------------------------------------------
+// step kernel with the contraction on the matrix cores (N <= 4, Np <= 16)
+//
+// Lanes are element-aligned: a wave holds 4 elements, lane 16q + j is node j
+// of element q.  The volume and lift terms of all three fields are one
+// product  R^T = X^T [Dr Ds LIFT]^T  per wave on v_mfma_f32_16x16x4f32:
+// rows are (element q, field f) pairs, columns are nodes, so lane 16q + j
+// receives R of element q at node j for f = 0..3 in its four accumulators.
+// X^T rows: f = 0..2 hold (-X_r, -X_s, dF) of h, hu, hv; f = 3 holds
+// (rx (B - B_k), sx (B - B_k), 0), whose product is dB/dx at the nodes; a
+// second, shorter pass over the Dr/Ds columns gives dB/dy.  The operator is
+// held in registers in B-operand order, 0 beyond Np rows / K columns.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+struct MShape {
+    static constexpr int Np = (N + 1) * (N + 2) / 2;
+    static constexpr int Nfp = N + 1;
+    static constexpr int nF = 3 * (N + 1);
+    static constexpr int KT = 2 * Np + nF;        // contraction length
+    static constexpr int KS = (KT + 3) / 4;       // MFMA steps of K = 4
+    static constexpr int KB = (2 * Np + 3) / 4;   // steps covering the Dr/Ds columns
+    static constexpr int RS = 4 * KS + 4;         // LDS row stride (floats)
+    static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
+};
+
+template <int KS>
+__device__ __forceinline__ int kperm(int k) {
+    // K index k is supplied by lane group k % 4 at step k / 4; each group's
+    // values are stored contiguously so a lane reads its row slice in order
+    return (k & 3) * KS + (k >> 2);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
+    using S = MShape<N>;
+    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KS = S::KS, KB = S::KB, RS = S::RS;
+    __shared__ float sA[16][4][RS];       // X^T rows per element (permuted K order)
+    __shared__ float sV[16][4][16];       // updated eta, hu, hv and B per node
+    __shared__ float sD[16][16];          // B - B_k per node
+    __shared__ float sG[16][4];           // rx, ry, sx, sy
+    __shared__ double sRed[16][16];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane >> 4, j = lane & 15;
+    const int el = wave * 4 + q;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = a.k_begin + blk * 16 + el;
+    const bool live = k < a.k_end;
+    const bool node = live && j < Np;
+    const long long KNp = a.KNp;
+    const float g = a.g, hvel = a.hvel;
+
+    for (int t = j; t < 4 * RS; t += 16) (&sA[el][0][0])[t] = 0.f;
+    float opB[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) opB[s] = a.ops.Amfma[s * 64 + lane];
+
+    LevelArgs L = a.lev[0];
+    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f;
+    float4 g0 = make_float4(0, 0, 0, 0), g3 = make_float4(0, 0, 0, 0);
+    const long long idx = (long long)k * Np + j;
+    if (live) {
+        L = pick_level(a, level_of(a, k));
+        const float4* gp = reinterpret_cast<const float4*>(a.geo) + 4LL * k;
+        g0 = gp[0];
+        g3 = gp[3];
+        if (j < Np) {
+            const float* Q = a.Q[L.parity];
+            eta = Q[idx];
+            hu = Q[KNp + idx];
+            hv = Q[2 * KNp + idx];
+            Bn = a.B[idx];
+        }
+    }
+    const float eta0 = __shfl(eta, lane & ~15);
+    const float B0 = __shfl(Bn, lane & ~15);
+    const float dlt = eta - eta0;
+
+    // ---- volume fluxes, written negated as X^T rows 0..2; bed gradient row 3
+    if (node) {
+        const float h = eta - Bn;
+        const float fv = vel_factor(h, hvel);
+        const float u = hu * fv, v = hv * fv;
+        const float p = 0.5f * g * (dlt * (2.f * h - dlt));
+        const float F[3] = {hu, hu * u + p, hu * v};
+        const float G[3] = {hv, hv * u, hv * v + p};
+        const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sA[el][c][kperm<KS>(j)] = -(rx * F[c] + ry * G[c]);
+            sA[el][c][kperm<KS>(Np + j)] = -(sx * F[c] + sy * G[c]);
+        }
+        const float bb = Bn - B0;
+        sA[el][3][kperm<KS>(j)] = rx * bb;
+        sA[el][3][kperm<KS>(Np + j)] = sx * bb;
+        sD[el][j] = bb;
+        if (j == 0) {
+            sG[el][0] = rx; sG[el][1] = ry; sG[el][2] = sx; sG[el][3] = sy;
+        }
+    }
+
+    // ---- face node fn = j of element q
+    const bool fnode = live && j < nF;
+    const int fn = j < nF ? j : 0;
+    const int f = fn / Nfp, jj = fn - f * Nfp;
+    const int n = a.ops.fmask[fn];
+    const float etaM = __shfl(eta, (lane & ~15) + n);
+    const float huM = __shfl(hu, (lane & ~15) + n);
+    const float hvM = __shfl(hv, (lane & ~15) + n);
+    const float BM = __shfl(Bn, (lane & ~15) + n);
+    float lamN = 0.f, nx = 0.f, ny = 0.f, fs = 0.f;
+    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f;
+    if (fnode) {
+        const float* gk = a.geo + 16LL * k;
+        nx = gk[4 + f];
+        ny = gk[7 + f];
+        fs = gk[10 + f];
+        const int4 cn = reinterpret_cast<const int4*>(a.conn)[k];
+        const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
+        if (nb < 0) {
+            const float mn = huM * nx + hvM * ny;
+            etaP = etaM;
+            BP = BM;
+            huP = huM - 2.f * mn * nx;
+            hvP = hvM - 2.f * mn * ny;
+        } else {
+            const int f2 = (cn.w >> (2 * f)) & 3;
+            const LevelArgs L2 = pick_level(a, level_of(a, nb));
+            const int n2 = a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
+            const long long id2 = (long long)nb * Np + n2;
+            BP = a.B[id2];
+            if (L2.active || a.half == nullptr) {
+                const float* Q2 = a.Q[L2.parity];
+                etaP = Q2[id2];
+                huP = Q2[KNp + id2];
+                hvP = Q2[2 * KNp + id2];
+            } else {
+                const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
+                etaP = a.half[hid];
+                huP = a.half[a.KnF + hid];
+                hvP = a.half[2 * a.KnF + hid];
+            }
+        }
+    }
+    const float hM = etaM - BM, hP = etaP - BP;
+    const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
+    const float uM = huM * fM, vM = hvM * fM, uP = huP * fP, vP = hvP * fP;
+    const float Bmax = fmaxf(BM, BP);
+    const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
+    const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
+    lamN = fnode ? fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP)) : 0.f;
+    float lam = lamN;
+    const int fbase = (lane & ~15) + f * Nfp;
+#pragma unroll
+    for (int t = 0; t < Nfp; ++t) lam = fmaxf(lam, __shfl(lamN, fbase + t));
+    if (fnode) {
+        const float dp = 0.25f * g * (hsM - hsP) * (hsM + hsP);
+        const float ah = hsM * unM + hsP * unP;
+        const float au = hsM * uM * unM + hsP * uP * unP;
+        const float av = hsM * vM * unM + hsP * vP * unP;
+        const int kp = kperm<KS>(2 * Np + fn);
+        sA[el][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah + 0.5f * lam * (hsP - hsM));
+        sA[el][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
+        sA[el][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
+    }
+    __syncthreads();
+
+    // ---- contraction on the matrix cores
+    const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
+    const int ag = lane >> 4;           // K group supplied by this lane
+    const float* arow = &sA[wave * 4 + (ar >> 2)][ar & 3][ag * KS];
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[s], opB[s], acc, 0, 0, 0);
+    floatx4 accy = {0.f, 0.f, 0.f, 0.f};
+    {
+        const int eA = wave * 4 + (ar >> 2);
+        const bool rowy = (ar & 3) == 0;
+        const float ry = sG[eA][1], sy = sG[eA][3];
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            const int kk = 4 * s + ag;
+            float av = 0.f;
+            if (rowy) av = kk < Np ? ry * sD[eA][kk] : (kk < 2 * Np ? sy * sD[eA][kk - Np] : 0.f);
+            accy = __builtin_amdgcn_mfma_f32_16x16x4f32(av, opB[s], accy, 0, 0, 0);
+        }
+    }
+    float Rn[3];
+    Rn[0] = acc[0];
+    Rn[1] = acc[1] - g * dlt * acc[3];
+    Rn[2] = acc[2] - g * dlt * accy[0];
+
+    // ---- Adams-Bashforth update
+    float qn[3] = {eta, hu, hv};
+    if (node) {
+        float* R0 = a.R[L.slot[0]];
+        R0[idx] = Rn[0];
+        R0[KNp + idx] = Rn[1];
+        R0[2 * KNp + idx] = Rn[2];
+        const float dt = g3.z * L.scale;
+        float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
+        if (L.ab[1] != 0.f) {
+            const float* R1 = a.R[L.slot[1]];
+            r1[0] = R1[idx]; r1[1] = R1[KNp + idx]; r1[2] = R1[2 * KNp + idx];
+        }
+        if (L.ab[2] != 0.f) {
+            const float* R2 = a.R[L.slot[2]];
+            r2[0] = R2[idx]; r2[1] = R2[KNp + idx]; r2[2] = R2[2 * KNp + idx];
+        }
+        const float q0[3] = {eta, hu, hv};
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
+        if (L.write_half && a.half != nullptr) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                const int slot = a.ops.nodeface[2 * j + sl];
+                if (slot < 0) continue;
+                const long long hid = (long long)k * nF + slot;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    a.half[c * a.KnF + hid] =
+                        q0[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]);
+            }
+        }
+        sV[el][0][j] = qn[0];
+        sV[el][1][j] = qn[1];
+        sV[el][2][j] = qn[2];
+        sV[el][3][j] = Bn;
+    }
+    __syncthreads();
+    // ---- per-element FP64 reductions: 0 min h, 1-3 means, 4-12 midpoint deviations
+    if (live && j < 13) {
+        double acc64;
+        if (j == 0) {
+            acc64 = 1e300;
+            for (int t = 0; t < Np; ++t) acc64 = fmin(acc64, (double)sV[el][0][t] - (double)sV[el][3][t]);
+        } else {
+            const int c = j < 4 ? j - 1 : (j - 4) / 3;
+            const double* w = j < 4 ? a.ops.wh : a.ops.pmid + ((j - 4) % 3) * Np;
+            acc64 = 0.0;
+            for (int t = 0; t < Np; ++t) {
+                const double val = c == 0 ? (double)sV[el][0][t] - (double)sV[el][3][t] : (double)sV[el][c][t];
+                acc64 += w[t] * val;
+            }
+        }
+        sRed[el][j] = acc64;
+    }
+    __syncthreads();
+    // ---- positivity limiter decision (Algorithm 5.2)
+    if (live && j == 0) {
+        const double hmin = sRed[el][0], hb = sRed[el][1];
+        double mean[3] = {hb, sRed[el][2], sRed[el][3]};
+        double scale = 1.0, hdry = 0.0;
+        int code = 0;
+        if (a.pp_on && hmin <= (double)a.eps) {
+            if (hb < (double)a.h0) {
+                code = 2;
+                if (hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
+                hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);
+                mean[0] = hdry;
+                mean[1] = 0.0;
+                mean[2] = 0.0;
+                scale = 0.0;
+            } else {
+                code = 1;
+                const double d0 = sRed[el][4], d1 = sRed[el][5], d2 = sRed[el][6];
+                const double Ssum = d0 + d1 + d2;
+                const double vmin = hb + fmin(Ssum - 2.0 * d0, fmin(Ssum - 2.0 * d1, Ssum - 2.0 * d2));
+                const double den = hb - vmin;
+                scale = den > 0.0 ? fmin(1.0, (hb - (double)a.h0) / den) : 1.0;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.means[c * (long long)a.K + k] = mean[c];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a.devs[t * (long long)a.K + k] = (float)(scale * sRed[el][4 + t]);
+        a.flags[k] = (uint8_t)code;
+        sRed[el][13] = (double)code;
+        sRed[el][14] = scale;
+        sRed[el][15] = hdry;
+    }
+    __syncthreads();
+    if (!node) return;
+    const int code = (int)sRed[el][13];
+    float out[3] = {qn[0], qn[1], qn[2]};
+    if (code == 2) {
+        out[0] = (float)(sRed[el][15] + (double)Bn);
+        out[1] = 0.f;
+        out[2] = 0.f;
+    } else if (code == 1) {
+        const double th = sRed[el][14];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double val = sRed[el][1 + c];
+#pragma unroll
+            for (int ed = 0; ed < 3; ++ed) val += th * sRed[el][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
             out[c] = c == 0 ? (float)(val + (double)Bn) : (float)val;
         }
     }
@@ -630,12 +942,23 @@ int step_elems_per_block(int N, int engine) {
 
 template <int N>
 static int launch_step_n(const StepArgs& a, hipStream_t s) {
-    const int E = Shape<N>::E;
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
+    if constexpr (N <= 4) {
+        if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_FUSED) {
+            hipLaunchKernelGGL(step_mfma_kernel<N>, dim3((n + 15) / 16), dim3(256), 0, s, a);
+            return check_launch("step mfma kernel");
+        }
+    }
+    const int E = Shape<N>::E;
     const int blocks = (n + E - 1) / E;
     hipLaunchKernelGGL(step_kernel<N>, dim3(blocks), dim3(256), 0, s, a);
     return check_launch("step kernel");
+}
+
+int mfma_steps(int N) {
+    const int Np = (N + 1) * (N + 2) / 2, nF = 3 * (N + 1);
+    return (2 * Np + nF + 3) / 4;
 }
 
 int launch_step(const StepArgs& a, void* stream, int elems_per_block) {

@@ -105,6 +105,7 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block);
 int launch_tvb(const TvbArgs& a, void* stream);
 int launch_diag(const DiagArgs& a, void* stream);
 int step_elems_per_block(int N, int engine);
+int mfma_steps(int N);   // K = 4 steps of the MFMA contraction (N <= 4)
 const char* device_error_string();
 
 }  // namespace dgswe

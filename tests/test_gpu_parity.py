@@ -11,6 +11,8 @@ from helpers import flag_flips, gpu_solver, log, oracle_solver, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+# contraction paths held to the same bounds: FP32 VALU matvecs and FP32 MFMA
+PATHS = ["fused_fp32", "fused_mfma32"]
 
 
 def _require_gpu():
@@ -45,24 +47,33 @@ def _compare(tag, wl, steps, precision="fused_fp32", tol=TOL, flip_frac=0.01, to
     return g, o, q
 
 
-def test_c1_one_step():
+@pytest.mark.parametrize("path", PATHS)
+def test_c1_one_step(path):
     """After one step the momentum is dt*R; FP32 storage of the depth (relative
     rounding 6e-8) differentiated by the nodal operators (about (N+1)^2/H) and
     scaled by g gives a relative momentum error of order 1e-5 against the FP64
     oracle, so the one-step bound on momentum is 1e-4 (depth: 1e-6)."""
-    _compare("c1-1", W.c1(), 1, tol=1e-6, tol_m=1e-4)
+    _compare("c1-1", W.c1(), 1, precision=path, tol=1e-6, tol_m=1e-4)
 
 
-def test_c1_trajectory_200_steps():
-    g, o, q = _compare("c1", W.c1(), 200)
+@pytest.mark.parametrize("path", PATHS)
+def test_c1_trajectory_200_steps(path):
+    g, o, q = _compare("c1", W.c1(), 200, precision=path)
     assert abs(g.diagnostics(0)["mass"] - o.mass()) <= 1e-6 * o.mass()
 
 
 def test_c1_tvd_limiter_branches():
-    """M = 0 turns the TVB limiter into its TVD form so that limiting happens."""
-    g, o, q = _compare("c1-tvd", W.c1(), 60, tvb_M=0.0, flip_frac=0.05)
+    """M = 0 turns the TVB limiter into its TVD form so that limiting happens
+    on smooth data.  Its keep-or-limit decision compares characteristic
+    increments that are nearly equal, so FP32 and FP64 take different branches
+    on a few elements (each such flip replaces a degree-N solution by its P1
+    part locally); the flips are counted and bounded, and the states agree to
+    the size of those local P1 truncations."""
+    g, o, q = _compare("c1-tvd", W.c1(), 60, tvb_M=0.0, flip_frac=0.05, tol=1e-4, tol_m=1e-2)
     tv = sum(fc[1] for fc in o.flag_counts)
     assert tv[2] + tv[3] > 0
+    d = g.diagnostics(0)
+    assert d["tvb_counts"][2] + d["tvb_counts"][3] > 0
 
 
 def test_plain_path_matches_fused_bitwise():
@@ -77,8 +88,9 @@ def test_plain_path_matches_fused_bitwise():
         assert np.array_equal(x, y)
 
 
-def test_wetdry_parity():
-    g, o, q = _compare("wetdry", W.small_wetdry(n=12, N=3), 100, flip_frac=0.03, tol=1e-4)
+@pytest.mark.parametrize("path", PATHS)
+def test_wetdry_parity(path):
+    g, o, q = _compare("wetdry", W.small_wetdry(n=12, N=3), 100, precision=path, flip_frac=0.01)
     d = g.diagnostics(0)
     assert d["min_depth"] >= 0.0
     assert d["pp_counts"][1] + d["pp_counts"][2] > 0
@@ -131,11 +143,12 @@ def test_checkpoint_resume_and_determinism():
         assert np.array_equal(x, y)
 
 
-def test_ensemble_matches_single_instances():
+@pytest.mark.parametrize("path", PATHS)
+def test_ensemble_matches_single_instances(path):
     _require_gpu()
     wl = W.c5(n_inst=3, kmin=400, kmax=3000)
-    log("[ensemble] Ks=" + str([i.etov.shape[0] for i in wl.instances]))
-    g = gpu_solver(wl)
+    log("[ensemble] Ks=" + str([i.etov.shape[0] for i in wl.instances]) + " path=" + path)
+    g = gpu_solver(wl, precision=path)
     g.advance(40)
     for i in range(3):
         o = oracle_solver(wl, inst=i)
@@ -144,14 +157,55 @@ def test_ensemble_matches_single_instances():
         o.run(40)
         err = rel_l2(o, np.stack(g.get_state(i)), o.q)
         log(f"[ensemble] inst {i} relL2 {err}")
-        assert err["h"] <= 1e-4 and err["m"] <= 1e-4
+        assert err["h"] <= 1e-5 and err["m"] <= 1e-5
 
 
-def test_bench_config_full_size_first_steps():
+@pytest.mark.parametrize("path", PATHS)
+def test_bench_config_full_size_first_steps(path):
     """The bench workload (131072 triangles, N=4, wet/dry) at full size in the
     benchmarked launch configuration: 10 steps against the oracle, plus the
-    invariants (h >= 0, mass)."""
-    g, o, q = _compare("c2-10", W.c2(), 10, tol=1e-5, flip_frac=0.002)
+    invariants (h >= 0, mass).  After 10 steps of dt = 1.3e-6 the momentum is
+    tiny and its relative error is set by the thin films on the dry beach,
+    whose surface level is stored next to a bed of about 0.2 (FP32 spacing
+    1.5e-8 against depths of 1e-5), so the momentum bound here is 1e-4; the
+    configured 500-step run is held to 1e-5 in test_bench_config_500_steps."""
+    g, o, q = _compare("c2-10", W.c2(), 10, precision=path, tol=1e-6, tol_m=1e-4, flip_frac=0.002)
     d = g.diagnostics(0)
     assert d["min_depth"] >= 0.0
     assert abs(d["mass"] - o.mass()) <= 1e-6 * o.mass()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_bench_config_500_steps(path):
+    """The bench workload for its configured 500 steps against the stored
+    FP64 oracle states of 1024 sampled elements (written by
+    tests/golden/make_golden.py): relative L2 <= 1e-5 on the sample,
+    mass within FP32 rounding of the oracle's."""
+    import os
+    _require_gpu()
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_samples.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle samples not generated")
+    z = np.load(path)
+    wl = W.c2()
+    log(f"[c2-500] K=131072 N=4 steps=500 path={path}")
+    g = gpu_solver(wl, precision=path)
+    g.advance(int(z["steps"]))
+    h, hu, hv = g.get_state(0)
+    idx = z["elements"]
+    M, J = z["mass_matrix"], z["J"]
+
+    def nrm(a):
+        return float(np.sum(J * np.einsum("ki,ij,kj->k", a, M, a)))
+
+    eh = np.sqrt(nrm(h[idx] - z["h"]) / nrm(z["h"]))
+    em = np.sqrt((nrm(hu[idx] - z["hu"]) + nrm(hv[idx] - z["hv"])) / (nrm(z["hu"]) + nrm(z["hv"])))
+    d = g.diagnostics(0)
+    flags = g.flags(0)
+    pp_flips = int(np.sum((flags & 3) != z["final_pp"]))
+    tv_flips = int(np.sum(((flags >> 2) & 3) != z["final_tvb"]))
+    log(f"[c2-500] relL2 h={eh:.3e} m={em:.3e} flips pp={pp_flips} tvb={tv_flips} "
+        f"mass gpu={d['mass']:.12e} oracle={float(z['mass']):.12e} neg={d['negative_means']}")
+    assert eh <= 1e-5 and em <= 1e-5
+    assert abs(d["mass"] - float(z["mass"])) <= 1e-6 * float(z["mass"])
+    assert pp_flips + tv_flips <= 0.002 * wl.n_elements
