@@ -447,8 +447,10 @@ class Solver:
             q, pp_new, neg = self.pp_limit(q, active)
             pp = np.where(active, pp_new, prev_pp)
         tv = np.zeros(K, dtype=np.uint8)
+        prev_tv = self.flags.tvb if self.flags is not None else tv
         if p.tvb:
-            q, tv = self.tvb_limit(q, pp, active)
+            q, tv_new = self.tvb_limit(q, pp, active)
+            tv = np.where(active, tv_new, prev_tv)
         return q, StepFlags(pp, tv, neg)
 
     # --------------------------------------------------------- diagnostics

@@ -447,7 +447,9 @@ struct MShape {
     static constexpr int KT = 2 * Np + nF;        // contraction length
     static constexpr int KS = (KT + 3) / 4;       // MFMA steps of K = 4
     static constexpr int KB = (2 * Np + 3) / 4;   // steps covering the Dr/Ds columns
-    static constexpr int RS = 4 * KS + 4;         // LDS row stride (floats)
+    // LDS row stride (floats); at least 24 so the rows can later hold the
+    // per-element reduction scratch
+    static constexpr int RS = (4 * KS + 4) > 24 ? (4 * KS + 4) : 24;
     static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
 };
 
@@ -462,11 +464,15 @@ template <int N>
 __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     using S = MShape<N>;
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KS = S::KS, KB = S::KB, RS = S::RS;
-    __shared__ float sA[16][4][RS];       // X^T rows per element (permuted K order)
-    __shared__ float sV[16][4][16];       // updated eta, hu, hv and B per node
+    // X^T rows per element (permuted K order); after the contraction the same
+    // storage holds the updated nodal values and the per-element reductions
+    __shared__ float sA[16][4][RS];
     __shared__ float sD[16][16];          // B - B_k per node
     __shared__ float sG[16][4];           // rx, ry, sx, sy
-    __shared__ double sRed[16][16];
+    static_assert(sizeof(float) * 16 * 4 * RS >= sizeof(float) * 16 * 4 * 16 + sizeof(double) * 16 * 16,
+                  "reduction scratch must fit in the X^T rows");
+    float (*sV)[4][16] = reinterpret_cast<float (*)[4][16]>(&sA[0][0][0]);
+    double (*sRed)[16] = reinterpret_cast<double (*)[16]>(&sA[0][0][0] + 16 * 4 * 16);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -478,29 +484,73 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const bool node = live && j < Np;
     const long long KNp = a.KNp;
     const float g = a.g, hvel = a.hvel;
+    const long long idx = (long long)k * Np + j;
 
-    for (int t = j; t < 4 * RS; t += 16) (&sA[el][0][0])[t] = 0.f;
-    float opB[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) opB[s] = a.ops.Amfma[s * 64 + lane];
-
+    // ---- issue every independent global load first
     LevelArgs L = a.lev[0];
     float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f;
+    float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
     float4 g0 = make_float4(0, 0, 0, 0), g3 = make_float4(0, 0, 0, 0);
-    const long long idx = (long long)k * Np + j;
+    int4 cn = make_int4(-1, -1, -1, 0);
+    const bool fnode = live && j < nF;
+    const int fn = j < nF ? j : 0;
+    const int f = fn / Nfp, jj = fn - f * Nfp;
+    float nx = 0.f, ny = 0.f, fs = 0.f;
     if (live) {
         L = pick_level(a, level_of(a, k));
         const float4* gp = reinterpret_cast<const float4*>(a.geo) + 4LL * k;
         g0 = gp[0];
         g3 = gp[3];
+        cn = reinterpret_cast<const int4*>(a.conn)[k];
         if (j < Np) {
             const float* Q = a.Q[L.parity];
             eta = Q[idx];
             hu = Q[KNp + idx];
             hv = Q[2 * KNp + idx];
             Bn = a.B[idx];
+            if (L.ab[1] != 0.f) {
+                const float* R1 = a.R[L.slot[1]];
+                r1[0] = R1[idx]; r1[1] = R1[KNp + idx]; r1[2] = R1[2 * KNp + idx];
+            }
+            if (L.ab[2] != 0.f) {
+                const float* R2 = a.R[L.slot[2]];
+                r2[0] = R2[idx]; r2[1] = R2[KNp + idx]; r2[2] = R2[2 * KNp + idx];
+            }
+        }
+        if (j < nF) {
+            const float* gk = a.geo + 16LL * k;
+            nx = gk[4 + f];
+            ny = gk[7 + f];
+            fs = gk[10 + f];
         }
     }
+    const int n = a.ops.fmask[fn];
+    // exterior trace of face node fn: neighbour gather (depends only on conn)
+    const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
+    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f;
+    if (fnode && nb >= 0) {
+        const int f2 = (cn.w >> (2 * f)) & 3;
+        const LevelArgs L2 = pick_level(a, level_of(a, nb));
+        const int n2 = a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
+        const long long id2 = (long long)nb * Np + n2;
+        BP = a.B[id2];
+        if (L2.active || a.half == nullptr) {
+            const float* Q2 = a.Q[L2.parity];
+            etaP = Q2[id2];
+            huP = Q2[KNp + id2];
+            hvP = Q2[2 * KNp + id2];
+        } else {
+            const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
+            etaP = a.half[hid];
+            huP = a.half[a.KnF + hid];
+            hvP = a.half[2 * a.KnF + hid];
+        }
+    }
+    float opB[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) opB[s] = a.ops.Amfma[s * 64 + lane];
+    for (int t = j; t < 4 * RS; t += 16) (&sA[el][0][0])[t] = 0.f;
+
     const float eta0 = __shfl(eta, lane & ~15);
     const float B0 = __shfl(Bn, lane & ~15);
     const float dlt = eta - eta0;
@@ -529,47 +579,16 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     }
 
     // ---- face node fn = j of element q
-    const bool fnode = live && j < nF;
-    const int fn = j < nF ? j : 0;
-    const int f = fn / Nfp, jj = fn - f * Nfp;
-    const int n = a.ops.fmask[fn];
     const float etaM = __shfl(eta, (lane & ~15) + n);
     const float huM = __shfl(hu, (lane & ~15) + n);
     const float hvM = __shfl(hv, (lane & ~15) + n);
     const float BM = __shfl(Bn, (lane & ~15) + n);
-    float lamN = 0.f, nx = 0.f, ny = 0.f, fs = 0.f;
-    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f;
-    if (fnode) {
-        const float* gk = a.geo + 16LL * k;
-        nx = gk[4 + f];
-        ny = gk[7 + f];
-        fs = gk[10 + f];
-        const int4 cn = reinterpret_cast<const int4*>(a.conn)[k];
-        const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
-        if (nb < 0) {
-            const float mn = huM * nx + hvM * ny;
-            etaP = etaM;
-            BP = BM;
-            huP = huM - 2.f * mn * nx;
-            hvP = hvM - 2.f * mn * ny;
-        } else {
-            const int f2 = (cn.w >> (2 * f)) & 3;
-            const LevelArgs L2 = pick_level(a, level_of(a, nb));
-            const int n2 = a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
-            const long long id2 = (long long)nb * Np + n2;
-            BP = a.B[id2];
-            if (L2.active || a.half == nullptr) {
-                const float* Q2 = a.Q[L2.parity];
-                etaP = Q2[id2];
-                huP = Q2[KNp + id2];
-                hvP = Q2[2 * KNp + id2];
-            } else {
-                const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
-                etaP = a.half[hid];
-                huP = a.half[a.KnF + hid];
-                hvP = a.half[2 * a.KnF + hid];
-            }
-        }
+    if (fnode && nb < 0) {
+        const float mn = huM * nx + hvM * ny;
+        etaP = etaM;
+        BP = BM;
+        huP = huM - 2.f * mn * nx;
+        hvP = hvM - 2.f * mn * ny;
     }
     const float hM = etaM - BM, hP = etaP - BP;
     const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
@@ -577,7 +596,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const float Bmax = fmaxf(BM, BP);
     const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
     const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
-    lamN = fnode ? fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP)) : 0.f;
+    const float lamN = fnode ? fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP)) : 0.f;
     float lam = lamN;
     const int fbase = (lane & ~15) + f * Nfp;
 #pragma unroll
@@ -621,21 +640,13 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 
     // ---- Adams-Bashforth update
     float qn[3] = {eta, hu, hv};
+    __syncthreads();   // X^T rows are consumed; their storage is reused below
     if (node) {
         float* R0 = a.R[L.slot[0]];
         R0[idx] = Rn[0];
         R0[KNp + idx] = Rn[1];
         R0[2 * KNp + idx] = Rn[2];
         const float dt = g3.z * L.scale;
-        float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
-        if (L.ab[1] != 0.f) {
-            const float* R1 = a.R[L.slot[1]];
-            r1[0] = R1[idx]; r1[1] = R1[KNp + idx]; r1[2] = R1[2 * KNp + idx];
-        }
-        if (L.ab[2] != 0.f) {
-            const float* R2 = a.R[L.slot[2]];
-            r2[0] = R2[idx]; r2[1] = R2[KNp + idx]; r2[2] = R2[2 * KNp + idx];
-        }
         const float q0[3] = {eta, hu, hv};
 #pragma unroll
         for (int c = 0; c < 3; ++c)

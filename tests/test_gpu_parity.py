@@ -183,10 +183,10 @@ def test_bench_config_500_steps(path):
     mass within FP32 rounding of the oracle's."""
     import os
     _require_gpu()
-    path = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_samples.npz")
-    if not os.path.exists(path):
+    golden = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_samples.npz")
+    if not os.path.exists(golden):
         pytest.skip("stored oracle samples not generated")
-    z = np.load(path)
+    z = np.load(golden)
     wl = W.c2()
     log(f"[c2-500] K=131072 N=4 steps=500 path={path}")
     g = gpu_solver(wl, precision=path)
@@ -209,3 +209,65 @@ def test_bench_config_500_steps(path):
     assert eh <= 1e-5 and em <= 1e-5
     assert abs(d["mass"] - float(z["mass"])) <= 1e-6 * float(z["mass"])
     assert pp_flips + tv_flips <= 0.002 * wl.n_elements
+
+
+def test_multirate_graded_bands():
+    """Multi-rate AB3 on a graded band mesh (4 levels) against the oracle's
+    tick schedule (Section 4, Algorithm 4.1): 6 coarse steps = 48 ticks."""
+    _require_gpu()
+    wl = W.c3(n0=3)
+    log(f"[mrab] K={wl.n_elements} levels=4")
+    g = gpu_solver(wl)
+    o = oracle_solver(wl)
+    lev, dt = g.levels(0)
+    assert np.array_equal(lev.astype(int), o.levels)
+    assert abs(dt - o.dt_min) <= 1e-12 * o.dt_min
+    g.advance(6)
+    o.run(6)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    pp, tv = flag_flips(g.flags(0), o.flags)
+    log(f"[mrab] relL2 h={err['h']:.3e} m={err['m']:.3e} flips pp={pp} tvb={tv}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert pp + tv == 0
+
+
+def test_multirate_graph_matches_eager():
+    _require_gpu()
+    wl = W.c3(n0=2)
+    log("[mrab-graph]")
+    a = gpu_solver(wl, use_graph=1)
+    b = gpu_solver(wl, use_graph=0)
+    a.advance(9)
+    b.advance(9)
+    for x, y in zip(a.get_state(0), b.get_state(0)):
+        assert np.array_equal(x, y)
+
+
+def test_degree5_reduced_c4():
+    """The N = 5 precision workload (16 Fourier modes, fully wet) on a reduced
+    128x64x2 mesh for 30 steps (VALU contraction: Np = 21 > 16)."""
+    _compare("c4-small", W.c4(nx=128, ny=64), 30)
+
+
+def test_full_ensemble_64_instances():
+    """The 64-instance ensemble (about 4.1M elements) advanced together for
+    its 200 steps; the three smallest instances are checked against the
+    oracle, all instances for h >= 0 and mass."""
+    _require_gpu()
+    wl = W.c5()
+    Ks = [i.etov.shape[0] for i in wl.instances]
+    log(f"[c5] total K={sum(Ks)} min={min(Ks)} max={max(Ks)}")
+    g = gpu_solver(wl, precision="fused_mfma32")
+    g.prepare()
+    m0 = [g.diagnostics(i)["mass"] for i in range(len(Ks))]
+    g.advance(wl.steps)
+    for i in range(len(Ks)):
+        d = g.diagnostics(i)
+        assert d["min_depth"] >= 0.0
+        assert abs(d["mass"] - m0[i]) <= 1e-6 * m0[i]
+    for i in np.argsort(Ks)[:3]:
+        o = oracle_solver(wl, inst=int(i))
+        o.run(wl.steps)
+        err = rel_l2(o, np.stack(g.get_state(int(i))), o.q)
+        log(f"[c5] inst {i} K={Ks[i]} relL2 h={err['h']:.3e} m={err['m']:.3e}")
+        assert err["h"] <= 1e-5 and err["m"] <= 1e-5
