@@ -39,7 +39,7 @@ struct Layout {
     size_t Q[2], R[3], half, means, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
     size_t B, geo, conn, stencil;
-    size_t Dr, Ds, LIFT, Amfma, fmask, nodeface, wh, pmid, phi, wfull;
+    size_t Dr, Ds, LIFT, Amfma, Wred, fmask, nodeface, wh, pmid, phi, wfull;
     size_t diag_partial, diag_out;
     size_t total;
 };
@@ -130,6 +130,7 @@ static void compute_layout(dg_solver* h) {
     l.Ds = take(size_t(Np) * Np * 4);
     l.LIFT = take(size_t(Np) * nF * 4);
     l.Amfma = take(size_t(64) * 256 * 4 * 2);
+    l.Wred = take(size_t(4) * 64 * 8);
     l.fmask = take(size_t(nF) * 4);
     l.nodeface = take(size_t(Np) * 2 * 4);
     l.wh = take(size_t(Np) * 8);
@@ -424,6 +425,17 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     HIPCHECK(up(l.Ds, Ds.data(), Ds.size() * 4));
     HIPCHECK(up(l.LIFT, LIFT.data(), LIFT.size() * 4));
     if (!amfma.empty()) HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
+    // FP64 MFMA A-operand of the element reductions: step s, lane l holds
+    // W[row l % 16][node 4 s + l / 16], rows 0: w/2, 1-3: P1 midpoint - mean
+    std::vector<double> wred(4 * 64, 0.0);
+    if (Np <= 16)
+        for (int st = 0; st < 4; ++st)
+            for (int ln = 0; ln < 64; ++ln) {
+                const int row = ln % 16, nd = 4 * st + ln / 16;
+                if (row > 3 || nd >= Np) continue;
+                wred[size_t(st) * 64 + ln] = row == 0 ? wh[nd] : pmid[(row - 1) * Np + nd];
+            }
+    HIPCHECK(up(l.Wred, wred.data(), wred.size() * 8));
     HIPCHECK(up(l.fmask, re.fmask.data(), re.fmask.size() * 4));
     HIPCHECK(up(l.nodeface, nodeface.data(), nodeface.size() * 4));
     HIPCHECK(up(l.wh, wh.data(), wh.size() * 8));
@@ -558,6 +570,9 @@ static StepArgs base_step_args(dg_solver* h) {
     a.ops.wh = reinterpret_cast<const double*>(h->ws + l.wh);
     a.ops.pmid = reinterpret_cast<const double*>(h->ws + l.pmid);
     a.ops.phi = reinterpret_cast<const double*>(h->ws + l.phi);
+    a.ops.Wred = reinterpret_cast<const double*>(h->ws + l.Wred);
+    a.stencil = reinterpret_cast<const float*>(h->ws + l.stencil);
+    a.tvb_on = (h->p.limiter_mask & DG_LIMIT_TVB) ? 1 : 0;
     a.g = float(h->p.g);
     a.h0 = float(h->p.h0);
     a.eps = float(h->p.eps);
@@ -827,7 +842,7 @@ int32_t dg_get_flags(dg_solver* h, int32_t inst, uint8_t* flags, void* stream) {
     std::vector<uint8_t> f(h->K);
     HIPCHECK(hipMemcpy(f.data(), h->ws + h->lay.flags, h->K, hipMemcpyDeviceToHost));
     const Inst& I = h->inst[inst];
-    for (int k = 0; k < I.mesh.K; ++k) flags[k] = f[h->inv[I.offset + k]];
+    for (int k = 0; k < I.mesh.K; ++k) flags[k] = f[h->inv[I.offset + k]] & 0x0F;
     return DG_OK;
 }
 

@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         for (int c = 0; c < 3; ++c) a.means[c * (long long)a.K + k] = mean[c];
 #pragma unroll
         for (int q = 0; q < 9; ++q) a.devs[q * (long long)a.K + k] = (float)(scale * sRed[e][4 + q]);
-        a.flags[k] = (uint8_t)code;
+        a.flags[k] = (uint8_t)(code | (code != 2 ? kTvbCandidate : 0));
         sRed[e][13] = (double)code;
         sRed[e][14] = scale;
         sRed[e][15] = hdry;
@@ -425,19 +425,39 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// characteristic rows L of the flux Jacobian in direction (ex, ey) at a cell
+// mean (Section 5.3, Cockburn-Shu): shared by the in-kernel TVB screen and
+// the TVB kernel so both take the same decision
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void char_left(double hb, double mu, double mv, double g, double ex,
+                                          double ey, double Lm[3][3]) {
+    const double ub = mu / hb, vb = mv / hb;
+    const double c = sqrt(g * hb);
+    const double un = ub * ex + vb * ey, ut = -ub * ey + vb * ex;
+    const double i2c = 0.5 / c;
+    Lm[0][0] = (un + c) * i2c; Lm[0][1] = -ex * i2c; Lm[0][2] = -ey * i2c;
+    Lm[1][0] = -ut;            Lm[1][1] = -ey;       Lm[1][2] = ex;
+    Lm[2][0] = -(un - c) * i2c; Lm[2][1] = ex * i2c; Lm[2][2] = ey * i2c;
+}
+
+// ---------------------------------------------------------------------------
 // step kernel with the contraction on the matrix cores (N <= 4, Np <= 16)
 //
 // Lanes are element-aligned: a wave holds 4 elements, lane 16q + j is node j
-// of element q.  The volume and lift terms of all three fields are one
-// product  R^T = X^T [Dr Ds LIFT]^T  per wave on v_mfma_f32_16x16x4f32:
-// rows are (element q, field f) pairs, columns are nodes, so lane 16q + j
-// receives R of element q at node j for f = 0..3 in its four accumulators.
-// X^T rows: f = 0..2 hold (-X_r, -X_s, dF) of h, hu, hv; f = 3 holds
-// (rx (B - B_k), sx (B - B_k), 0), whose product is dB/dx at the nodes; a
-// second, shorter pass over the Dr/Ds columns gives dB/dy.  The operator is
-// held in registers in B-operand order, 0 beyond Np rows / K columns.
+// of element q, and every LDS row a wave touches is its own, so waves only
+// order their own LDS traffic (no block barriers).
+// Contraction: R^T = X^T [Dr Ds LIFT]^T on v_mfma_f32_16x16x4f32 with rows
+// (element q, field f) and columns = nodes, so lane 16q + j receives R of
+// element q at node j for f = 0..3.  X^T rows: 0..2 = (-X_r, -X_s, dF) of h,
+// hu, hv; 3 = (rx (B - B_k), sx (B - B_k), 0) giving dB/dx; a second pass over
+// the Dr/Ds columns with row 4 = (ry (B - B_k), sy (B - B_k)) gives dB/dy.
+// Element reductions (means and P1 edge-midpoint deviations of h, hu, hv) are
+// W V on v_mfma_f64_16x16x4f64 in FP64 (W rows: w/2 and the three midpoint
+// functionals).  A TVB screen in FP64 marks the elements whose characteristic
+// midpoint increments all stay within M d^2 (kept without neighbour data).
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int N>
 struct MShape {
@@ -447,32 +467,43 @@ struct MShape {
     static constexpr int KT = 2 * Np + nF;        // contraction length
     static constexpr int KS = (KT + 3) / 4;       // MFMA steps of K = 4
     static constexpr int KB = (2 * Np + 3) / 4;   // steps covering the Dr/Ds columns
-    // LDS row stride (floats); at least 24 so the rows can later hold the
-    // per-element reduction scratch
-    static constexpr int RS = (4 * KS + 4) > 24 ? (4 * KS + 4) : 24;
+    static constexpr int KSP = (KS + 3) & ~3;     // steps padded to whole float4 reads
+    static constexpr int RS = 4 * KSP + 4;        // LDS row stride (floats)
     static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
 };
 
-template <int KS>
+template <int KSP>
 __device__ __forceinline__ int kperm(int k) {
     // K index k is supplied by lane group k % 4 at step k / 4; each group's
-    // values are stored contiguously so a lane reads its row slice in order
-    return (k & 3) * KS + (k >> 2);
+    // values are contiguous so a lane reads its row slice with float4 loads
+    return (k & 3) * KSP + (k >> 2);
 }
 
-template <int N>
+__device__ __forceinline__ void wave_lds_sync() {
+    // order this wave's LDS writes before its reads of other lanes' data
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// element load at a 32-bit element index from a uniform base
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, unsigned i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
+}
+
+template <int N, bool MULTI>
 __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     using S = MShape<N>;
-    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KS = S::KS, KB = S::KB, RS = S::RS;
-    // X^T rows per element (permuted K order); after the contraction the same
-    // storage holds the updated nodal values and the per-element reductions
-    __shared__ float sA[16][4][RS];
-    __shared__ float sD[16][16];          // B - B_k per node
-    __shared__ float sG[16][4];           // rx, ry, sx, sy
-    static_assert(sizeof(float) * 16 * 4 * RS >= sizeof(float) * 16 * 4 * 16 + sizeof(double) * 16 * 16,
-                  "reduction scratch must fit in the X^T rows");
-    float (*sV)[4][16] = reinterpret_cast<float (*)[4][16]>(&sA[0][0][0]);
-    double (*sRed)[16] = reinterpret_cast<double (*)[16]>(&sA[0][0][0] + 16 * 4 * 16);
+    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KT = S::KT, KS = S::KS, KB = S::KB;
+    constexpr int KSP = S::KSP, RS = S::RS;
+    __shared__ __attribute__((aligned(16))) float sA[16][5][RS];
+    __shared__ double sVd[16][3][16];     // updated h, hu, hv per node (FP64)
+    __shared__ double sRed[16][16];       // 0 min h, 1-3 means, 4-12 deviations, 13-15 PP result
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -482,83 +513,88 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const int k = a.k_begin + blk * 16 + el;
     const bool live = k < a.k_end;
     const bool node = live && j < Np;
-    const long long KNp = a.KNp;
+    const unsigned KNp = (unsigned)a.KNp;
     const float g = a.g, hvel = a.hvel;
-    const long long idx = (long long)k * Np + j;
+    const unsigned idx = (unsigned)k * Np + j;
 
-    // ---- issue every independent global load first
+    // ---- independent global loads first
     LevelArgs L = a.lev[0];
+    if (MULTI && live) L = pick_level(a, level_of(a, k));
+    const float* Qi = a.Q[L.parity];
     float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f;
     float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
-    float4 g0 = make_float4(0, 0, 0, 0), g3 = make_float4(0, 0, 0, 0);
+    float4 g0 = make_float4(0, 0, 0, 0);
+    float dtmin = 0.f;
     int4 cn = make_int4(-1, -1, -1, 0);
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
     const int f = fn / Nfp, jj = fn - f * Nfp;
     float nx = 0.f, ny = 0.f, fs = 0.f;
     if (live) {
-        L = pick_level(a, level_of(a, k));
-        const float4* gp = reinterpret_cast<const float4*>(a.geo) + 4LL * k;
-        g0 = gp[0];
-        g3 = gp[3];
-        cn = reinterpret_cast<const int4*>(a.conn)[k];
+        g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * k);
+        dtmin = ldg(a.geo, 16u * k + 14u);
+        cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)k);
         if (j < Np) {
-            const float* Q = a.Q[L.parity];
-            eta = Q[idx];
-            hu = Q[KNp + idx];
-            hv = Q[2 * KNp + idx];
-            Bn = a.B[idx];
+            eta = ldg(Qi, idx);
+            hu = ldg(Qi + KNp, idx);
+            hv = ldg(Qi + 2 * (size_t)KNp, idx);
+            Bn = ldg(a.B, idx);
             if (L.ab[1] != 0.f) {
                 const float* R1 = a.R[L.slot[1]];
-                r1[0] = R1[idx]; r1[1] = R1[KNp + idx]; r1[2] = R1[2 * KNp + idx];
+                r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
             }
             if (L.ab[2] != 0.f) {
                 const float* R2 = a.R[L.slot[2]];
-                r2[0] = R2[idx]; r2[1] = R2[KNp + idx]; r2[2] = R2[2 * KNp + idx];
+                r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
             }
         }
         if (j < nF) {
-            const float* gk = a.geo + 16LL * k;
-            nx = gk[4 + f];
-            ny = gk[7 + f];
-            fs = gk[10 + f];
+            nx = ldg(a.geo, 16u * k + 4u + f);
+            ny = ldg(a.geo, 16u * k + 7u + f);
+            fs = ldg(a.geo, 16u * k + 10u + f);
         }
     }
     const int n = a.ops.fmask[fn];
-    // exterior trace of face node fn: neighbour gather (depends only on conn)
     const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
     float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f;
     if (fnode && nb >= 0) {
         const int f2 = (cn.w >> (2 * f)) & 3;
-        const LevelArgs L2 = pick_level(a, level_of(a, nb));
-        const int n2 = a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
-        const long long id2 = (long long)nb * Np + n2;
-        BP = a.B[id2];
-        if (L2.active || a.half == nullptr) {
-            const float* Q2 = a.Q[L2.parity];
-            etaP = Q2[id2];
-            huP = Q2[KNp + id2];
-            hvP = Q2[2 * KNp + id2];
+        const unsigned id2 = (unsigned)nb * Np + a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
+        BP = ldg(a.B, id2);
+        const float* Q2 = Qi;
+        bool from_half = false;
+        if (MULTI) {
+            const LevelArgs L2 = pick_level(a, level_of(a, nb));
+            Q2 = a.Q[L2.parity];
+            from_half = !L2.active && a.half != nullptr;
+        }
+        if (!from_half) {
+            etaP = ldg(Q2, id2);
+            huP = ldg(Q2 + KNp, id2);
+            hvP = ldg(Q2 + 2 * (size_t)KNp, id2);
         } else {
-            const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
-            etaP = a.half[hid];
-            huP = a.half[a.KnF + hid];
-            hvP = a.half[2 * a.KnF + hid];
+            const unsigned hid = (unsigned)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
+            const unsigned KnF = (unsigned)a.KnF;
+            etaP = ldg(a.half, hid);
+            huP = ldg(a.half + KnF, hid);
+            hvP = ldg(a.half + 2 * (size_t)KnF, hid);
         }
     }
     float opB[KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) opB[s] = a.ops.Amfma[s * 64 + lane];
-    for (int t = j; t < 4 * RS; t += 16) (&sA[el][0][0])[t] = 0.f;
+    for (int s = 0; s < KS; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
+    double wred[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) wred[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
 
     const float eta0 = __shfl(eta, lane & ~15);
     const float B0 = __shfl(Bn, lane & ~15);
     const float dlt = eta - eta0;
 
-    // ---- volume fluxes, written negated as X^T rows 0..2; bed gradient row 3
+    // ---- X^T rows: volume fluxes (negated), bed-gradient rows, zero padding
     if (node) {
         const float h = eta - Bn;
-        const float fv = vel_factor(h, hvel);
+        const float fv = 2.f * h * __builtin_amdgcn_rcpf(h * h + fmaxf(h * h, hvel * hvel));
         const float u = hu * fv, v = hv * fv;
         const float p = 0.5f * g * (dlt * (2.f * h - dlt));
         const float F[3] = {hu, hu * u + p, hu * v};
@@ -566,19 +602,25 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sA[el][c][kperm<KS>(j)] = -(rx * F[c] + ry * G[c]);
-            sA[el][c][kperm<KS>(Np + j)] = -(sx * F[c] + sy * G[c]);
+            sA[el][c][kperm<KSP>(j)] = -(rx * F[c] + ry * G[c]);
+            sA[el][c][kperm<KSP>(Np + j)] = -(sx * F[c] + sy * G[c]);
         }
         const float bb = Bn - B0;
-        sA[el][3][kperm<KS>(j)] = rx * bb;
-        sA[el][3][kperm<KS>(Np + j)] = sx * bb;
-        sD[el][j] = bb;
-        if (j == 0) {
-            sG[el][0] = rx; sG[el][1] = ry; sG[el][2] = sx; sG[el][3] = sy;
-        }
+        sA[el][3][kperm<KSP>(j)] = rx * bb;
+        sA[el][3][kperm<KSP>(Np + j)] = sx * bb;
+        sA[el][4][kperm<KSP>(j)] = ry * bb;
+        sA[el][4][kperm<KSP>(Np + j)] = sy * bb;
+    }
+    if (j < nF) {   // lift columns of the bed rows are zero
+        sA[el][3][kperm<KSP>(2 * Np + j)] = 0.f;
+        sA[el][4][kperm<KSP>(2 * Np + j)] = 0.f;
+    }
+    if (j < 4 * KSP - KT) {   // K padding of all rows
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sA[el][c][kperm<KSP>(KT + j)] = 0.f;
     }
 
-    // ---- face node fn = j of element q
+    // ---- face node fn = j of element q: reconstructed states, LLF flux
     const float etaM = __shfl(eta, (lane & ~15) + n);
     const float huM = __shfl(hu, (lane & ~15) + n);
     const float hvM = __shfl(hv, (lane & ~15) + n);
@@ -591,12 +633,15 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         hvP = hvM - 2.f * mn * ny;
     }
     const float hM = etaM - BM, hP = etaP - BP;
-    const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
+    const float fM = 2.f * hM * __builtin_amdgcn_rcpf(hM * hM + fmaxf(hM * hM, hvel * hvel));
+    const float fP = 2.f * hP * __builtin_amdgcn_rcpf(hP * hP + fmaxf(hP * hP, hvel * hvel));
     const float uM = huM * fM, vM = hvM * fM, uP = huP * fP, vP = hvP * fP;
     const float Bmax = fmaxf(BM, BP);
     const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
     const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
-    const float lamN = fnode ? fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP)) : 0.f;
+    const float lamN = fnode ? fmaxf(fabsf(unM) + __builtin_amdgcn_sqrtf(g * hsM),
+                                     fabsf(unP) + __builtin_amdgcn_sqrtf(g * hsP))
+                             : 0.f;
     float lam = lamN;
     const int fbase = (lane & ~15) + f * Nfp;
 #pragma unroll
@@ -606,91 +651,90 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         const float ah = hsM * unM + hsP * unP;
         const float au = hsM * uM * unM + hsP * uP * unP;
         const float av = hsM * vM * unM + hsP * vP * unP;
-        const int kp = kperm<KS>(2 * Np + fn);
+        const int kp = kperm<KSP>(2 * Np + fn);
         sA[el][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah + 0.5f * lam * (hsP - hsM));
         sA[el][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
         sA[el][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
     }
-    __syncthreads();
+    wave_lds_sync();
 
     // ---- contraction on the matrix cores
     const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
     const int ag = lane >> 4;           // K group supplied by this lane
-    const float* arow = &sA[wave * 4 + (ar >> 2)][ar & 3][ag * KS];
+    const int eA = wave * 4 + (ar >> 2);
+    float av[KSP], ay[KSP];
+#pragma unroll
+    for (int s4 = 0; s4 < KSP / 4; ++s4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(&sA[eA][ar & 3][ag * KSP + 4 * s4]);
+        const float4 y4 = *reinterpret_cast<const float4*>(&sA[eA][4][ag * KSP + 4 * s4]);
+        av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
+        ay[4 * s4] = y4.x; ay[4 * s4 + 1] = y4.y; ay[4 * s4 + 2] = y4.z; ay[4 * s4 + 3] = y4.w;
+    }
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[s], opB[s], acc, 0, 0, 0);
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
     floatx4 accy = {0.f, 0.f, 0.f, 0.f};
-    {
-        const int eA = wave * 4 + (ar >> 2);
-        const bool rowy = (ar & 3) == 0;
-        const float ry = sG[eA][1], sy = sG[eA][3];
+    const bool rowy = (ar & 3) == 0;
 #pragma unroll
-        for (int s = 0; s < KB; ++s) {
-            const int kk = 4 * s + ag;
-            float av = 0.f;
-            if (rowy) av = kk < Np ? ry * sD[eA][kk] : (kk < 2 * Np ? sy * sD[eA][kk - Np] : 0.f);
-            accy = __builtin_amdgcn_mfma_f32_16x16x4f32(av, opB[s], accy, 0, 0, 0);
-        }
-    }
+    for (int s = 0; s < KB; ++s)
+        accy = __builtin_amdgcn_mfma_f32_16x16x4f32(rowy ? ay[s] : 0.f, opB[s], accy, 0, 0, 0);
     float Rn[3];
     Rn[0] = acc[0];
     Rn[1] = acc[1] - g * dlt * acc[3];
     Rn[2] = acc[2] - g * dlt * accy[0];
 
-    // ---- Adams-Bashforth update
+    // ---- Adams-Bashforth update, RHS ring, half-step traces
     float qn[3] = {eta, hu, hv};
-    __syncthreads();   // X^T rows are consumed; their storage is reused below
     if (node) {
         float* R0 = a.R[L.slot[0]];
-        R0[idx] = Rn[0];
-        R0[KNp + idx] = Rn[1];
-        R0[2 * KNp + idx] = Rn[2];
-        const float dt = g3.z * L.scale;
+        stg(R0, idx, Rn[0]);
+        stg(R0 + KNp, idx, Rn[1]);
+        stg(R0 + 2 * (size_t)KNp, idx, Rn[2]);
+        const float dt = dtmin * L.scale;
         const float q0[3] = {eta, hu, hv};
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
-        if (L.write_half && a.half != nullptr) {
+        if (MULTI && L.write_half && a.half != nullptr) {
+            const unsigned KnF = (unsigned)a.KnF;
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
                 const int slot = a.ops.nodeface[2 * j + sl];
                 if (slot < 0) continue;
-                const long long hid = (long long)k * nF + slot;
+                const unsigned hid = (unsigned)k * nF + slot;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    a.half[c * a.KnF + hid] =
-                        q0[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]);
+                    stg(a.half + c * (size_t)KnF, hid,
+                        q0[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]));
             }
         }
-        sV[el][0][j] = qn[0];
-        sV[el][1][j] = qn[1];
-        sV[el][2][j] = qn[2];
-        sV[el][3][j] = Bn;
     }
-    __syncthreads();
-    // ---- per-element FP64 reductions: 0 min h, 1-3 means, 4-12 midpoint deviations
-    if (live && j < 13) {
-        double acc64;
-        if (j == 0) {
-            acc64 = 1e300;
-            for (int t = 0; t < Np; ++t) acc64 = fmin(acc64, (double)sV[el][0][t] - (double)sV[el][3][t]);
-        } else {
-            const int c = j < 4 ? j - 1 : (j - 4) / 3;
-            const double* w = j < 4 ? a.ops.wh : a.ops.pmid + ((j - 4) % 3) * Np;
-            acc64 = 0.0;
-            for (int t = 0; t < Np; ++t) {
-                const double val = c == 0 ? (double)sV[el][0][t] - (double)sV[el][3][t] : (double)sV[el][c][t];
-                acc64 += w[t] * val;
-            }
+    // ---- FP64 element reductions on the matrix cores, min depth by shuffles
+    const double h64 = node ? (double)qn[0] - (double)Bn : 0.0;
+    sVd[el][0][j] = h64;
+    sVd[el][1][j] = node ? (double)qn[1] : 0.0;
+    sVd[el][2][j] = node ? (double)qn[2] : 0.0;
+    double hmin = node ? h64 : 1e300;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, 16));
+    wave_lds_sync();
+    doublex4 red = {0.0, 0.0, 0.0, 0.0};
+    {
+        const int c = lane & 15;          // column: element c/4, field c%4
+        const int ec = wave * 4 + (c >> 2), fc = c & 3;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const double bv = fc < 3 ? sVd[ec][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
+            red = __builtin_amdgcn_mfma_f64_16x16x4f64(wred[s], bv, red, 0, 0, 0);
         }
-        sRed[el][j] = acc64;
+        // lane 16 g + c holds row g (0: mean, 1-3: midpoint deviation g-1) of column c
+        if (fc < 3) sRed[ec][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
     }
-    __syncthreads();
+    if (j == 0) sRed[el][0] = hmin;
+    wave_lds_sync();
     // ---- positivity limiter decision (Algorithm 5.2)
     if (live && j == 0) {
-        const double hmin = sRed[el][0], hb = sRed[el][1];
-        double mean[3] = {hb, sRed[el][2], sRed[el][3]};
+        const double hb = sRed[el][1];
         double scale = 1.0, hdry = 0.0;
         int code = 0;
         if (a.pp_on && hmin <= (double)a.eps) {
@@ -698,9 +742,6 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
                 code = 2;
                 if (hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
                 hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);
-                mean[0] = hdry;
-                mean[1] = 0.0;
-                mean[2] = 0.0;
                 scale = 0.0;
             } else {
                 code = 1;
@@ -711,37 +752,59 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
                 scale = den > 0.0 ? fmin(1.0, (hb - (double)a.h0) / den) : 1.0;
             }
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.means[c * (long long)a.K + k] = mean[c];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) a.devs[t * (long long)a.K + k] = (float)(scale * sRed[el][4 + t]);
-        a.flags[k] = (uint8_t)code;
         sRed[el][13] = (double)code;
         sRed[el][14] = scale;
         sRed[el][15] = hdry;
     }
-    __syncthreads();
-    if (!node) return;
+    wave_lds_sync();
     const int code = (int)sRed[el][13];
+    const double scale = sRed[el][14], hdry = sRed[el][15];
+    // post-limiter means
+    const double mean0 = code == 2 ? hdry : sRed[el][1];
+    const double mean1 = code == 2 ? 0.0 : sRed[el][2];
+    const double mean2 = code == 2 ? 0.0 : sRed[el][3];
+    // ---- TVB screen: lane j < 9 checks component j % 3 of edge j / 3
+    bool small = true;
+    float devw = 0.f;
+    if (live && j < 9) {
+        const int ed = j / 3, r = j % 3;
+        devw = (float)(scale * sRed[el][4 + 3 * r + ed]);   // deviation of field r at edge ed
+        if (a.tvb_on && code != 2) {
+            const float* st = a.stencil + 16u * k;
+            double Lm[3][3];
+            char_left(mean0, mean1, mean2, (double)g, (double)st[4 * ed + 2], (double)st[4 * ed + 3], Lm);
+            const double d0 = (double)(float)(scale * sRed[el][4 + ed]);
+            const double d1 = (double)(float)(scale * sRed[el][7 + ed]);
+            const double d2 = (double)(float)(scale * sRed[el][10 + ed]);
+            const double a1 = Lm[r][0] * d0 + Lm[r][1] * d1 + Lm[r][2] * d2;
+            small = fabs(a1) <= (double)st[12];
+        }
+    }
+    const unsigned long long bal = __ballot(small);
+    const bool candidate = a.tvb_on && code != 2 && ((bal >> (16 * q)) & 0x1FFull) != 0x1FFull;
+    if (live && j < 3) stg(a.means, (unsigned)j * (unsigned)a.K + k, j == 0 ? mean0 : (j == 1 ? mean1 : mean2));
+    if (candidate && j < 9) stg(a.devs, (unsigned)(3 * (j % 3) + j / 3) * (unsigned)a.K + k, devw);
+    if (live && j == 0) a.flags[k] = (uint8_t)(code | (candidate ? kTvbCandidate : 0));
+    if (!node) return;
+    // ---- limited nodal values and the new state
     float out[3] = {qn[0], qn[1], qn[2]};
     if (code == 2) {
-        out[0] = (float)(sRed[el][15] + (double)Bn);
+        out[0] = (float)(hdry + (double)Bn);
         out[1] = 0.f;
         out[2] = 0.f;
     } else if (code == 1) {
-        const double th = sRed[el][14];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double val = sRed[el][1 + c];
 #pragma unroll
-            for (int ed = 0; ed < 3; ++ed) val += th * sRed[el][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
+            for (int ed = 0; ed < 3; ++ed) val += scale * sRed[el][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
             out[c] = c == 0 ? (float)(val + (double)Bn) : (float)val;
         }
     }
     float* Qo = a.Q[1 - L.parity];
-    Qo[idx] = out[0];
-    Qo[KNp + idx] = out[1];
-    Qo[2 * KNp + idx] = out[2];
+    stg(Qo, idx, out[0]);
+    stg(Qo + KNp, idx, out[1]);
+    stg(Qo + 2 * (size_t)KNp, idx, out[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,7 +814,8 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const int k = a.k_begin + blockIdx.x * 256 + threadIdx.x;
     if (k >= a.k_end) return;
     const int K = a.K;
-    const uint8_t pp = a.flags[k] & 3;
+    const uint8_t fl = a.flags[k];
+    const uint8_t pp = fl & 3;
     if (pp == 2) {
         a.flags[k] = pp;
         return;
@@ -764,6 +828,10 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
             a.flags[k] = pp;
             return;
         }
+    if (!(fl & kTvbCandidate)) {   // every characteristic increment within M d^2
+        a.flags[k] = pp | (1 << 2);
+        return;
+    }
     const double qb[3] = {a.means[k], a.means[(long long)K + k], a.means[2LL * K + k]};
     double dev[3][3];
 #pragma unroll
@@ -801,11 +869,8 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         double dbar[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) dbar[q] = aj * diff[pj][q] + ak * diff[pk][q];
-        const double un = ub * ex + vb * ey, ut = -ub * ey + vb * ex;
-        const double i2c = 0.5 / c;
-        const double Lm[3][3] = {{(un + c) * i2c, -ex * i2c, -ey * i2c},
-                                 {-ut, -ey, ex},
-                                 {-(un - c) * i2c, ex * i2c, ey * i2c}};
+        double Lm[3][3];
+        char_left(qb[0], qb[1], qb[2], a.g, ex, ey, Lm);
         const double Rm[3][3] = {{1.0, 0.0, 1.0},
                                  {ub - c * ex, -ey, ub + c * ex},
                                  {vb - c * ey, ex, vb + c * ey}};
@@ -957,7 +1022,10 @@ static int launch_step_n(const StepArgs& a, hipStream_t s) {
     if (n <= 0) return 0;
     if constexpr (N <= 4) {
         if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_FUSED) {
-            hipLaunchKernelGGL(step_mfma_kernel<N>, dim3((n + 15) / 16), dim3(256), 0, s, a);
+            if (a.nlev > 1)
+                hipLaunchKernelGGL((step_mfma_kernel<N, true>), dim3((n + 15) / 16), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((step_mfma_kernel<N, false>), dim3((n + 15) / 16), dim3(256), 0, s, a);
             return check_launch("step mfma kernel");
         }
     }

@@ -8,6 +8,9 @@
 namespace dgswe {
 
 constexpr int kMaxLevels = 6;
+// flag bit set by the step kernels: the element needs the full TVB limiter
+// (not dry, and some characteristic midpoint increment exceeds M d^2)
+constexpr int kTvbCandidate = 16;
 
 // Kernel modes of the step kernel.
 enum StepMode : int {
@@ -41,6 +44,7 @@ struct DevOps {
     const double* wh;      // Np: w / 2 (cell-mean weights)
     const double* pmid;    // 3 x Np: P1 midpoint value minus mean
     const double* phi;     // 3 x Np: midpoint-Lagrange P1 basis at the nodes
+    const double* Wred;    // FP64 MFMA A-operand of [w/2; P1 midpoint - mean] (4 x 64)
 };
 
 struct StepArgs {
@@ -62,8 +66,9 @@ struct StepArgs {
     uint8_t* flags;        // [K]
     unsigned long long* counters;  // [0] negative-mean events
     DevOps ops;
+    const float* stencil;  // [K][16] TVB stencil (in-kernel screen)
     float g, h0, eps, hvel;
-    int pp_on, dry_literal;
+    int pp_on, dry_literal, tvb_on;
 };
 
 struct TvbArgs {
