@@ -64,11 +64,13 @@ def copy_reference(n_bytes: int = 1 << 29, reps: int = 5):
 
 
 def step_kernel_bytes(Np: int) -> int:
-    """Algorithmic HBM bytes per element of one fused step-kernel launch:
-    state read+write 2*3*Np*4, bed Np*4, RHS ring 1 write + 2 reads 3*3*Np*4,
-    geometry 64, connectivity 16, FP64 means 24, midpoint deviations 36,
-    flag 1.  Neighbour face values (halo) are not counted."""
-    return 64 * Np + 141
+    """Algorithmic HBM bytes per element of one single-rate step (what the
+    method has to move, each array once, FP32 nodal data): state h, hu, hv
+    read + write 2*3*Np*4, bed Np*4, RHS history 1 write + 2 reads 3*3*Np*4,
+    geometry 14 floats, connectivity 16, FP64 means 24, flag 1.  Neighbour
+    face values (halo), the low word of the compensated surface level and the
+    TVB deviations of candidate elements are implementation traffic on top."""
+    return 64 * Np + 97
 
 
 def make_solver(wl, precision, use_graph=1):

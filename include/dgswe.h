@@ -166,7 +166,8 @@ int32_t dg_prepare(dg_solver* h, void* stream);
 int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 
 /* Current state of instance `inst` as FP64 depth and momenta ([K][Np]).
- * Synchronises `stream`. */
+ * On the device the surface level is an FP32 pair hi + lo (relative to a
+ * per-instance datum) and the momenta are FP32.  Synchronises `stream`. */
 int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double* hv,
                      void* stream);
 

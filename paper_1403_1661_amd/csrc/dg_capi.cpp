@@ -70,7 +70,7 @@ struct dg_solver {
     bool bound = false, prepared = false;
     int device = 0;
     // host staging (sorted order, FP32)
-    std::vector<float> geo, stencil, Bh, Qh;   // Qh: [3][K*Np]; Bh, Qh[0] relative to the datum
+    std::vector<float> geo, stencil, Bh, Qh;   // Qh: [4][K*Np] (eta hi, hu, hv, eta lo); Bh, eta relative to the datum
     std::vector<double> B64;                   // bed elevation, FP64, sorted order
     std::vector<int> conn;
     // time stepping state
@@ -112,12 +112,12 @@ static void compute_layout(dg_solver* h) {
     };
     const size_t KNp = size_t(h->K) * h->Np, KnF = size_t(h->K) * h->nF;
     l.dyn_begin = o;
-    l.Q[0] = take(3 * KNp * 4);
-    l.Q[1] = take(3 * KNp * 4);
+    l.Q[0] = take(4 * KNp * 4);
+    l.Q[1] = take(4 * KNp * 4);
     for (int s = 0; s < 3; ++s) l.R[s] = take(3 * KNp * 4);
     l.half = take(h->L > 1 ? 3 * KnF * 4 : 0);
     l.means = take(3 * size_t(h->K) * 8);
-    l.devs = take(9 * size_t(h->K) * 4);
+    l.devs = take(9 * size_t(h->K) * 8);
     l.flags = take(size_t(h->K));
     l.counters = take(64);
     l.dyn_end = o;
@@ -482,7 +482,7 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
     if (!I.has_B) return fail(DG_ESTATE, "set the bathymetry of the instance first");
     const int Np = h->Np;
     const size_t KNp = size_t(h->K) * Np;
-    if (h->Qh.empty()) h->Qh.assign(3 * KNp, 0.f);
+    if (h->Qh.empty()) h->Qh.assign(4 * KNp, 0.f);
     double amax = 0.0, eta_sum = 0.0;
     long long n_wet = 0;
     for (int k = 0; k < I.mesh.K; ++k) {
@@ -502,8 +502,9 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
             amax = std::fmax(amax, std::sqrt(u * u + v * v) + std::sqrt(h->p.g * d));
         }
     }
-    // datum: mean wet surface level, rounded to FP32
-    I.datum = n_wet ? float(eta_sum / double(n_wet)) : 0.f;
+    // datum: mean wet surface level on the 2^-22 grid, so that a bed given on
+    // that grid within distance 4 of the datum is exact in FP32 after the shift
+    I.datum = n_wet ? float(std::ldexp(std::nearbyint(std::ldexp(eta_sum / double(n_wet), 22)), -22)) : 0.f;
     const double datum = double(I.datum);
     for (int k = 0; k < I.mesh.K; ++k) {
         const int s = h->inv[I.offset + k];
@@ -514,17 +515,23 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
             // caller's data (still water given as h = eta0 - B) does not reach
             // the finely rounded eta - datum; a dry node stores its bed value
             // and no node stores a surface below its bed
+            // the level is stored as an FP32 pair hi + lo (compensated sum)
             const float bs = float(b - datum);
-            float es = bs;
+            float es = bs, el = 0.f;
             if (hh[src] > 0.0) {
                 const double eta = hh[src] + b;
                 const double snapped = std::fabs(eta) < 4096.0 ? std::nearbyint(eta * 0x1p40) * 0x1p-40 : eta;
-                es = std::fmax(float(snapped - datum), bs);
+                const double v = snapped - datum;
+                if (v > double(bs)) {
+                    es = float(v);
+                    el = float(v - double(es));
+                }
             }
             h->Bh[dst] = bs;
             h->Qh[dst] = es;
             h->Qh[KNp + dst] = float(hu[src]);
             h->Qh[2 * KNp + dst] = float(hv[src]);
+            h->Qh[3 * KNp + dst] = el;
         }
     }
     double rmin = I.mesh.inradius[0];
@@ -558,7 +565,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
     a.conn = reinterpret_cast<const int*>(h->ws + l.conn);
     a.means = reinterpret_cast<double*>(h->ws + l.means);
-    a.devs = reinterpret_cast<float*>(h->ws + l.devs);
+    a.devs = reinterpret_cast<double*>(h->ws + l.devs);
     a.flags = reinterpret_cast<uint8_t*>(h->ws + l.flags);
     a.counters = reinterpret_cast<unsigned long long*>(h->ws + l.counters);
     a.ops.Dr = reinterpret_cast<const float*>(h->ws + l.Dr);
@@ -814,11 +821,11 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
     const int Np = h->Np;
     const size_t KNp = size_t(h->K) * Np;
     const Inst& I = h->inst[inst];
-    std::vector<float> q(3 * KNp), b(KNp);
+    std::vector<float> q(4 * KNp), b(KNp);
     for (int l = 0; l < h->L; ++l) {
         const size_t b0 = size_t(h->lev_begin[l]) * Np, n = size_t(h->lev_end[l] - h->lev_begin[l]) * Np;
         if (!n) continue;
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 4; ++c)
             HIPCHECK(hipMemcpy(q.data() + c * KNp + b0, h->ws + h->lay.Q[h->parity[l]] + (c * KNp + b0) * 4,
                                n * 4, hipMemcpyDeviceToHost));
     }
@@ -827,7 +834,7 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
         const size_t sidx = size_t(h->inv[I.offset + k]);
         for (int j = 0; j < Np; ++j) {
             const size_t src = sidx * Np + j, dst = size_t(k) * Np + j;
-            hh[dst] = double(q[src]) - double(b[src]);
+            hh[dst] = double(q[src]) - double(b[src]) + double(q[3 * KNp + src]);
             hu[dst] = double(q[KNp + src]);
             hv[dst] = double(q[2 * KNp + src]);
         }

@@ -1,8 +1,8 @@
 // HIP kernels (gfx950) of the nodal DG shallow-water step.
 //
 // Step kernel (one workgroup = E consecutive elements, one lane per node):
-//   1. stage eta, hu, hv, B of the block's elements in LDS (coalesced
-//      element-major loads);
+//   1. stage eta (an FP32 hi + lo pair), hu, hv, B of the block's elements
+//      in LDS (coalesced element-major loads);
 //   2. volume fluxes at the nodes in contravariant form X_r = rx F + ry G,
 //      velocities 2 h m / (h^2 + max(h^2, hvel^2)) (m/h for h >= hvel),
 //      X_s = sx F + sy G (Section 2, Eq. 2.3), with the momentum pressure and
@@ -58,6 +58,36 @@ __device__ __forceinline__ float vel_factor(float h, float hvel) {
     return 2.f * h / (h2 + fmaxf(h2, hvel * hvel));
 }
 
+// Compensated surface level: the state keeps eta as an FP32 pair hi + lo with
+// |lo| <= ulp(hi)/2, so that rounding the stored level to FP32 once per step
+// does not accumulate over a run.  eta_add adds an increment with the
+// two-sum of Knuth (the rounding error of hi + d is recovered exactly) and
+// renormalises with the fast two-sum of Dekker; eta_split rounds an FP64
+// value to the pair.
+__device__ __forceinline__ void eta_add(float& hi, float& lo, float d) {
+    const float s = hi + d;
+    const float bp = s - hi;
+    const float err = (hi - (s - bp)) + (d - bp);
+    const float l = lo + err;
+    hi = s + l;
+    lo = l - (hi - s);
+}
+
+__device__ __forceinline__ void eta_split(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+// Jump h*- - h*+ of the reconstructed depths (Eq. 5.1).  Where both sides
+// are wet they share max(B-, B+), so the jump is the difference of the two
+// compensated surface levels, formed without rounding the O(1) depths first
+// (the level difference of nearby values is exact in FP32); where one side
+// is clipped to zero the plain difference has no cancellation.
+__device__ __forceinline__ float depth_jump(float etaM, float loM, float etaP, float loP,
+                                            float hsM, float hsP) {
+    return (hsM > 0.f && hsP > 0.f) ? (etaM - etaP) + (loM - loP) : hsM - hsP;
+}
+
 template <typename A>
 __device__ __forceinline__ int level_of(const A& a, int k) {
     int l = 0;
@@ -84,9 +114,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, E = S::E;
     __shared__ float sDr[Np * Np], sDs[Np * Np], sL[Np * nF];
     __shared__ int sFm[nF];
-    __shared__ float sQ[4][E * Np];       // eta, hu, hv, B
+    __shared__ float sQ[5][E * Np];       // eta (hi), hu, hv, B, eta (lo)
     __shared__ float sX[7][E * Np];       // X_r (3 fields), X_s (3 fields), B - B_k
-    __shared__ float sT[4][E * nF];       // exterior eta, hu, hv, B
+    __shared__ float sT[5][E * nF];       // exterior eta (hi), hu, hv, B, eta (lo)
     __shared__ float sLam[E * nF];
     __shared__ float sF[3][E * nF];
     __shared__ double sRed[E][16];
@@ -114,7 +144,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     const float g = a.g, hvel = a.hvel;
 
     LevelArgs L = a.lev[0];
-    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f;
+    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f, lo = 0.f;
     float4 g0 = make_float4(0, 0, 0, 0), g3 = make_float4(0, 0, 0, 0);
     const long long idx = (long long)k * Np + i;
     if (live) {
@@ -123,11 +153,13 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         eta = Q[idx];
         hu = Q[KNp + idx];
         hv = Q[2 * KNp + idx];
+        lo = Q[3 * KNp + idx];
         Bn = a.B[idx];
         sQ[0][tid] = eta;
         sQ[1][tid] = hu;
         sQ[2][tid] = hv;
         sQ[3][tid] = Bn;
+        sQ[4][tid] = lo;
         const float4* gp = reinterpret_cast<const float4*>(a.geo) + 4LL * k;
         g0 = gp[0];   // rx, ry, sx, sy
         g3 = gp[3];   // fs2, J, dt_min of the instance, instance id
@@ -139,8 +171,8 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     if (rhs) {
         // ---- volume fluxes at the nodes
         if (live) {
-            const float h = eta - Bn;
-            dlt = eta - sQ[0][e * Np];
+            const float h = (eta - Bn) + lo;
+            dlt = (eta - sQ[0][e * Np]) + (lo - sQ[4][e * Np]);
             // bed relative to the element's first node: the gradient of B is
             // taken from O(H |grad B|) values instead of O(|B|) ones
             sX[6][tid] = Bn - sQ[3][e * Np];
@@ -172,12 +204,14 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             const int n = sFm[fn];
             const float etaM = sQ[0][fe * Np + n], huM = sQ[1][fe * Np + n];
             const float hvM = sQ[2][fe * Np + n], BM = sQ[3][fe * Np + n];
-            float etaP, huP, hvP, BP;
+            const float loM = sQ[4][fe * Np + n];
+            float etaP, huP, hvP, BP, loP = 0.f;
             if (nb < 0) {
                 const float* gk = a.geo + 16LL * kk;
                 const float nx = gk[4 + f], ny = gk[7 + f];
                 const float mn = huM * nx + hvM * ny;
                 etaP = etaM;
+                loP = loM;
                 BP = BM;
                 huP = huM - 2.f * mn * nx;
                 hvP = hvM - 2.f * mn * ny;
@@ -193,6 +227,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                     etaP = Q2[id2];
                     huP = Q2[KNp + id2];
                     hvP = Q2[2 * KNp + id2];
+                    loP = Q2[3 * KNp + id2];
                 } else {
                     const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - j);
                     etaP = a.half[hid];
@@ -204,15 +239,16 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             sT[1][t] = huP;
             sT[2][t] = hvP;
             sT[3][t] = BP;
+            sT[4][t] = loP;
             // nodal wave speed of the reconstructed states
             const float* gk = a.geo + 16LL * kk;
             const float nx = gk[4 + f], ny = gk[7 + f];
-            const float hM = etaM - BM, hP = etaP - BP;
+            const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
             const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
             const float uM = huM * fM, vM = hvM * fM;
             const float uP = huP * fP, vP = hvP * fP;
             const float Bmax = fmaxf(BM, BP);
-            const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
+            const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
             const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
             sLam[t] = fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP));
         }
@@ -231,24 +267,26 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             const float etaM = sQ[0][fe * Np + n], huM = sQ[1][fe * Np + n];
             const float hvM = sQ[2][fe * Np + n], BM = sQ[3][fe * Np + n];
             const float etaP = sT[0][t], huP = sT[1][t], hvP = sT[2][t], BP = sT[3][t];
+            const float loM = sQ[4][fe * Np + n], loP = sT[4][t];
             const float* gk = a.geo + 16LL * kk;
             const float nx = gk[4 + f], ny = gk[7 + f], fs = gk[10 + f];
-            const float hM = etaM - BM, hP = etaP - BP;
+            const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
             const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
             const float uM = huM * fM, vM = hvM * fM;
             const float uP = huP * fP, vP = hvP * fP;
             const float Bmax = fmaxf(BM, BP);
-            const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
+            const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
             const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
             // F(Q-).n - F*.n.  The (g/2)(h-)^2 of F(Q-).n cancels the one in the
             // pressure correction of Eq. 5.2, and the remaining (g/2) h*^2 terms
             // combine into (g/4)(h*- - h*+)(h*- + h*+): no O(1) quantities are
             // subtracted, and the difference is exactly zero for still water.
-            const float dp = 0.25f * g * (hsM - hsP) * (hsM + hsP);
+            const float dh = depth_jump(etaM, loM, etaP, loP, hsM, hsP);
+            const float dp = 0.25f * g * dh * (hsM + hsP);
             const float ah = hsM * unM + hsP * unP;
             const float au = hsM * uM * unM + hsP * uP * unP;
             const float av = hsM * vM * unM + hsP * vP * unP;
-            sF[0][t] = fs * ((huM * nx + hvM * ny) - 0.5f * ah + 0.5f * lam * (hsP - hsM));
+            sF[0][t] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
             sF[1][t] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
             sF[2][t] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
         }
@@ -292,6 +330,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     }
     // ---- Adams-Bashforth update
     float qn[3] = {eta, hu, hv};
+    float qlo = lo;
     if (live && mode != MODE_LIMIT_ONLY) {
         float* R0 = a.R[L.slot[0]];
         if (mode == MODE_UPDATE_ONLY) {
@@ -314,8 +353,11 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             r2[0] = R2[idx]; r2[1] = R2[KNp + idx]; r2[2] = R2[2 * KNp + idx];
         }
         const float q0[3] = {eta, hu, hv};
+        const float q0lo[3] = {lo, 0.f, 0.f};
+        const float d0 = dt * (L.ab[0] * Rn[0] + L.ab[1] * r1[0] + L.ab[2] * r2[0]);
+        eta_add(qn[0], qlo, d0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 1; c < 3; ++c)
             qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
         if (L.write_half && a.half != nullptr) {
 #pragma unroll
@@ -326,7 +368,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     a.half[c * a.KnF + hid] =
-                        q0[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]);
+                        q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]));
             }
         }
     }
@@ -335,6 +377,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         sQ[0][tid] = qn[0];
         sQ[1][tid] = qn[1];
         sQ[2][tid] = qn[2];
+        sQ[4][tid] = qlo;
     }
     __syncthreads();
     // ---- per-element FP64 reductions: 0 min h, 1-3 means, 4-12 midpoint deviations
@@ -344,12 +387,12 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             if (q == 0) {
                 acc = 1e300;
                 for (int j = 0; j < Np; ++j)
-                    acc = fmin(acc, (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]);
+                    acc = fmin(acc, (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]);
             } else if (q < 4) {
                 const int c = q - 1;
                 acc = 0.0;
                 for (int j = 0; j < Np; ++j) {
-                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]
+                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]
                                               : (double)sQ[c][e * Np + j];
                     acc += a.ops.wh[j] * val;
                 }
@@ -357,7 +400,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 const int c = (q - 4) / 3, ed = (q - 4) % 3;
                 acc = 0.0;
                 for (int j = 0; j < Np; ++j) {
-                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]
+                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]
                                               : (double)sQ[c][e * Np + j];
                     acc += a.ops.pmid[ed * Np + j] * val;
                 }
@@ -394,7 +437,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.means[c * (long long)a.K + k] = mean[c];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) a.devs[q * (long long)a.K + k] = (float)(scale * sRed[e][4 + q]);
+        for (int q = 0; q < 9; ++q) a.devs[q * (long long)a.K + k] = scale * sRed[e][4 + q];
         a.flags[k] = (uint8_t)(code | (code != 2 ? kTvbCandidate : 0));
         sRed[e][13] = (double)code;
         sRed[e][14] = scale;
@@ -404,8 +447,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     if (!live) return;
     const int code = (int)sRed[e][13];
     float out[3] = {qn[0], qn[1], qn[2]};
+    float olo = qlo;
     if (code == 2) {
-        out[0] = (float)(sRed[e][15] + (double)Bn);
+        eta_split(sRed[e][15] + (double)Bn, out[0], olo);
         out[1] = 0.f;
         out[2] = 0.f;
     } else if (code == 1) {
@@ -415,13 +459,17 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             double val = sRed[e][1 + c];
 #pragma unroll
             for (int ed = 0; ed < 3; ++ed) val += th * sRed[e][4 + 3 * c + ed] * a.ops.phi[ed * Np + i];
-            out[c] = c == 0 ? (float)(val + (double)Bn) : (float)val;
+            if (c == 0)
+                eta_split(val + (double)Bn, out[0], olo);
+            else
+                out[c] = (float)val;
         }
     }
     float* Qo = a.Q[1 - L.parity];
     Qo[idx] = out[0];
     Qo[KNp + idx] = out[1];
     Qo[2 * KNp + idx] = out[2];
+    Qo[3 * KNp + idx] = olo;
 }
 
 // ---------------------------------------------------------------------------
@@ -521,7 +569,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     LevelArgs L = a.lev[0];
     if (MULTI && live) L = pick_level(a, level_of(a, k));
     const float* Qi = a.Q[L.parity];
-    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f;
+    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f, lo = 0.f;
     float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
     float4 g0 = make_float4(0, 0, 0, 0);
     float dtmin = 0.f;
@@ -538,6 +586,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             eta = ldg(Qi, idx);
             hu = ldg(Qi + KNp, idx);
             hv = ldg(Qi + 2 * (size_t)KNp, idx);
+            lo = ldg(Qi + 3 * (size_t)KNp, idx);
             Bn = ldg(a.B, idx);
             if (L.ab[1] != 0.f) {
                 const float* R1 = a.R[L.slot[1]];
@@ -556,7 +605,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     }
     const int n = a.ops.fmask[fn];
     const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
-    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f;
+    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f, loP = 0.f;
     if (fnode && nb >= 0) {
         const int f2 = (cn.w >> (2 * f)) & 3;
         const unsigned id2 = (unsigned)nb * Np + a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
@@ -572,6 +621,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             etaP = ldg(Q2, id2);
             huP = ldg(Q2 + KNp, id2);
             hvP = ldg(Q2 + 2 * (size_t)KNp, id2);
+            loP = ldg(Q2 + 3 * (size_t)KNp, id2);
         } else {
             const unsigned hid = (unsigned)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
             const unsigned KnF = (unsigned)a.KnF;
@@ -588,12 +638,13 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     for (int s = 0; s < 4; ++s) wred[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
 
     const float eta0 = __shfl(eta, lane & ~15);
+    const float lo0 = __shfl(lo, lane & ~15);
     const float B0 = __shfl(Bn, lane & ~15);
-    const float dlt = eta - eta0;
+    const float dlt = (eta - eta0) + (lo - lo0);
 
     // ---- X^T rows: volume fluxes (negated), bed-gradient rows, zero padding
     if (node) {
-        const float h = eta - Bn;
+        const float h = (eta - Bn) + lo;
         const float fv = 2.f * h * __builtin_amdgcn_rcpf(h * h + fmaxf(h * h, hvel * hvel));
         const float u = hu * fv, v = hv * fv;
         const float p = 0.5f * g * (dlt * (2.f * h - dlt));
@@ -625,19 +676,21 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const float huM = __shfl(hu, (lane & ~15) + n);
     const float hvM = __shfl(hv, (lane & ~15) + n);
     const float BM = __shfl(Bn, (lane & ~15) + n);
+    const float loM = __shfl(lo, (lane & ~15) + n);
     if (fnode && nb < 0) {
         const float mn = huM * nx + hvM * ny;
         etaP = etaM;
+        loP = loM;
         BP = BM;
         huP = huM - 2.f * mn * nx;
         hvP = hvM - 2.f * mn * ny;
     }
-    const float hM = etaM - BM, hP = etaP - BP;
+    const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
     const float fM = 2.f * hM * __builtin_amdgcn_rcpf(hM * hM + fmaxf(hM * hM, hvel * hvel));
     const float fP = 2.f * hP * __builtin_amdgcn_rcpf(hP * hP + fmaxf(hP * hP, hvel * hvel));
     const float uM = huM * fM, vM = hvM * fM, uP = huP * fP, vP = hvP * fP;
     const float Bmax = fmaxf(BM, BP);
-    const float hsM = fmaxf(0.f, etaM - Bmax), hsP = fmaxf(0.f, etaP - Bmax);
+    const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
     const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
     const float lamN = fnode ? fmaxf(fabsf(unM) + __builtin_amdgcn_sqrtf(g * hsM),
                                      fabsf(unP) + __builtin_amdgcn_sqrtf(g * hsP))
@@ -647,12 +700,13 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 #pragma unroll
     for (int t = 0; t < Nfp; ++t) lam = fmaxf(lam, __shfl(lamN, fbase + t));
     if (fnode) {
-        const float dp = 0.25f * g * (hsM - hsP) * (hsM + hsP);
+        const float dh = depth_jump(etaM, loM, etaP, loP, hsM, hsP);
+        const float dp = 0.25f * g * dh * (hsM + hsP);
         const float ah = hsM * unM + hsP * unP;
         const float au = hsM * uM * unM + hsP * uP * unP;
         const float av = hsM * vM * unM + hsP * vP * unP;
         const int kp = kperm<KSP>(2 * Np + fn);
-        sA[el][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah + 0.5f * lam * (hsP - hsM));
+        sA[el][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
         sA[el][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
         sA[el][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
     }
@@ -685,6 +739,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 
     // ---- Adams-Bashforth update, RHS ring, half-step traces
     float qn[3] = {eta, hu, hv};
+    float qlo = lo;
     if (node) {
         float* R0 = a.R[L.slot[0]];
         stg(R0, idx, Rn[0]);
@@ -692,8 +747,10 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         stg(R0 + 2 * (size_t)KNp, idx, Rn[2]);
         const float dt = dtmin * L.scale;
         const float q0[3] = {eta, hu, hv};
+        const float q0lo[3] = {lo, 0.f, 0.f};
+        eta_add(qn[0], qlo, dt * (L.ab[0] * Rn[0] + L.ab[1] * r1[0] + L.ab[2] * r2[0]));
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 1; c < 3; ++c)
             qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
         if (MULTI && L.write_half && a.half != nullptr) {
             const unsigned KnF = (unsigned)a.KnF;
@@ -705,12 +762,12 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     stg(a.half + c * (size_t)KnF, hid,
-                        q0[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]));
+                        q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c])));
             }
         }
     }
     // ---- FP64 element reductions on the matrix cores, min depth by shuffles
-    const double h64 = node ? (double)qn[0] - (double)Bn : 0.0;
+    const double h64 = node ? (double)qn[0] - (double)Bn + (double)qlo : 0.0;
     sVd[el][0][j] = h64;
     sVd[el][1][j] = node ? (double)qn[1] : 0.0;
     sVd[el][2][j] = node ? (double)qn[2] : 0.0;
@@ -765,17 +822,17 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const double mean2 = code == 2 ? 0.0 : sRed[el][3];
     // ---- TVB screen: lane j < 9 checks component j % 3 of edge j / 3
     bool small = true;
-    float devw = 0.f;
+    double devw = 0.0;
     if (live && j < 9) {
         const int ed = j / 3, r = j % 3;
-        devw = (float)(scale * sRed[el][4 + 3 * r + ed]);   // deviation of field r at edge ed
+        devw = scale * sRed[el][4 + 3 * r + ed];   // deviation of field r at edge ed
         if (a.tvb_on && code != 2) {
             const float* st = a.stencil + 16u * k;
             double Lm[3][3];
             char_left(mean0, mean1, mean2, (double)g, (double)st[4 * ed + 2], (double)st[4 * ed + 3], Lm);
-            const double d0 = (double)(float)(scale * sRed[el][4 + ed]);
-            const double d1 = (double)(float)(scale * sRed[el][7 + ed]);
-            const double d2 = (double)(float)(scale * sRed[el][10 + ed]);
+            const double d0 = scale * sRed[el][4 + ed];
+            const double d1 = scale * sRed[el][7 + ed];
+            const double d2 = scale * sRed[el][10 + ed];
             const double a1 = Lm[r][0] * d0 + Lm[r][1] * d1 + Lm[r][2] * d2;
             small = fabs(a1) <= (double)st[12];
         }
@@ -788,8 +845,9 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     if (!node) return;
     // ---- limited nodal values and the new state
     float out[3] = {qn[0], qn[1], qn[2]};
+    float olo = qlo;
     if (code == 2) {
-        out[0] = (float)(hdry + (double)Bn);
+        eta_split(hdry + (double)Bn, out[0], olo);
         out[1] = 0.f;
         out[2] = 0.f;
     } else if (code == 1) {
@@ -798,13 +856,17 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             double val = sRed[el][1 + c];
 #pragma unroll
             for (int ed = 0; ed < 3; ++ed) val += scale * sRed[el][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
-            out[c] = c == 0 ? (float)(val + (double)Bn) : (float)val;
+            if (c == 0)
+                eta_split(val + (double)Bn, out[0], olo);
+            else
+                out[c] = (float)val;
         }
     }
     float* Qo = a.Q[1 - L.parity];
     stg(Qo, idx, out[0]);
     stg(Qo + KNp, idx, out[1]);
     stg(Qo + 2 * (size_t)KNp, idx, out[2]);
+    stg(Qo + 3 * (size_t)KNp, idx, olo);
 }
 
 // ---------------------------------------------------------------------------
@@ -813,31 +875,56 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const int k = a.k_begin + blockIdx.x * 256 + threadIdx.x;
     if (k >= a.k_end) return;
-    const int K = a.K;
+    const unsigned K = (unsigned)a.K;
+    // round 1: everything indexed by k alone
     const uint8_t fl = a.flags[k];
+    const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)k);
     const uint8_t pp = fl & 3;
     if (pp == 2) {
         a.flags[k] = pp;
         return;
     }
-    const int4 cn = reinterpret_cast<const int4*>(a.conn)[k];
-    const int nbs[3] = {cn.x, cn.y, cn.z};
+    const bool cand = (fl & kTvbCandidate) != 0;
+    double qb[3] = {0.0, 0.0, 0.0};
+    double dev[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    float st[16];
+    if (cand) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-        if (nbs[f] >= 0 && (a.flags[nbs[f]] & 3) == 2) {
-            a.flags[k] = pp;
-            return;
+        for (int c = 0; c < 3; ++c) qb[c] = ldg(a.means, c * K + k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int ed = 0; ed < 3; ++ed) dev[c][ed] = ldg(a.devs, (3 * c + ed) * K + k);
+        const float4* s4 = reinterpret_cast<const float4*>(a.stencil) + 4u * k;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4 v = s4[t];
+            st[4 * t] = v.x; st[4 * t + 1] = v.y; st[4 * t + 2] = v.z; st[4 * t + 3] = v.w;
         }
-    if (!(fl & kTvbCandidate)) {   // every characteristic increment within M d^2
+    }
+    // round 2: neighbours (flags, and means for candidates)
+    const int nbs[3] = {cn.x, cn.y, cn.z};
+    bool nb_dry = false;
+    double nbm[3][3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int nb = nbs[f];
+        if (nb >= 0) {
+            nb_dry = nb_dry || ((a.flags[nb] & 3) == 2);
+            if (cand) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nbm[f][c] = ldg(a.means, c * K + (unsigned)nb);
+            }
+        }
+    }
+    if (nb_dry) {
+        a.flags[k] = pp;
+        return;
+    }
+    if (!cand) {   // every characteristic increment within M d^2
         a.flags[k] = pp | (1 << 2);
         return;
     }
-    const double qb[3] = {a.means[k], a.means[(long long)K + k], a.means[2LL * K + k]};
-    double dev[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int ed = 0; ed < 3; ++ed) dev[c][ed] = (double)a.devs[(3 * c + ed) * (long long)K + k];
     const float* gk = a.geo + 16LL * k;
     double diff[3][3];   // [face][field]
 #pragma unroll
@@ -850,10 +937,9 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
             diff[f][2] = -2.0 * mn * ny;
         } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) diff[f][c] = a.means[c * (long long)K + nbs[f]] - qb[c];
+            for (int c = 0; c < 3; ++c) diff[f][c] = nbm[f][c] - qb[c];
         }
     }
-    const float* st = a.stencil + 16LL * k;
     const int pairs = __float_as_int(st[13]);
     const double M2 = st[12];
     const double hb = qb[0];
@@ -932,7 +1018,10 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         const double p0 = a.phi[j], p1 = a.phi[Np + j], p2 = a.phi[2 * Np + j];
         const long long id = (long long)k * Np + j;
         const double hval = qb[0] + D[0][0] * p0 + D[0][1] * p1 + D[0][2] * p2;
-        Qo[id] = (float)(hval + (double)a.B[id]);
+        float hi, lo;
+        eta_split(hval + (double)a.B[id], hi, lo);
+        Qo[id] = hi;
+        Qo[3 * a.KNp + id] = lo;
         Qo[a.KNp + id] = (float)(qb[1] + D[1][0] * p0 + D[1][1] * p1 + D[1][2] * p2);
         Qo[2 * a.KNp + id] = (float)(qb[2] + D[2][0] * p0 + D[2][1] * p1 + D[2][2] * p2);
     }
@@ -959,7 +1048,7 @@ __global__ void __launch_bounds__(256) diag_partial_kernel(DiagArgs a) {
         double wh = 0.0;
         for (int j = 0; j < a.Np; ++j) {
             const long long id = (long long)k * a.Np + j;
-            const double h = (double)Q[id] - (double)a.B[id];
+            const double h = (double)Q[id] - (double)a.B[id] + (double)Q[3 * a.KNp + id];
             wh += a.wfull[j] * h;
             hmin = fmin(hmin, h);
         }

@@ -55,14 +55,14 @@ struct StepArgs {
     int k_begin, k_end;    // element range of this launch
     int nlev;
     LevelArgs lev[kMaxLevels];
-    float* Q[2];           // ping-pong state buffers [3][K*Np]: eta, hu, hv
+    float* Q[2];           // ping-pong state buffers [4][K*Np]: eta (hi), hu, hv, eta (lo)
     const float* B;        // [K*Np]
     float* R[3];           // ring slots [3][K*Np]
     float* half;           // [3][K*3Nfp] half-step face traces (multi-rate) or null
     const float* geo;      // [K][16]
     const int* conn;       // [K][4]
     double* means;         // [3][K]
-    float* devs;           // [9][K]
+    double* devs;          // [9][K] P1 edge-midpoint deviations (TVB candidates)
     uint8_t* flags;        // [K]
     unsigned long long* counters;  // [0] negative-mean events
     DevOps ops;
@@ -84,7 +84,7 @@ struct TvbArgs {
     const int* conn;
     const float* stencil;  // [K][16]
     const double* means;
-    const float* devs;
+    const double* devs;
     uint8_t* flags;
     const double* phi;     // 3 x Np
     double g, h0, nu;
@@ -93,7 +93,7 @@ struct TvbArgs {
 struct DiagArgs {
     int K, Np, k_begin, k_end, inst;
     long long KNp;
-    const float* Q;        // state buffer [3][K*Np] (per element parity resolved by caller)
+    const float* Q;        // state buffer [4][K*Np] (per element parity resolved by caller)
     const float* Q2;       // second buffer
     const int* parity_of;  // null: all from Q; else per-level parity via lev table
     int nlev;

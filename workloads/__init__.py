@@ -25,6 +25,10 @@ Workloads (all seeded with ``numpy.random.default_rng(seed)``):
           200 steps each.
 
 Bathymetry ``B`` is bed elevation; the free surface is ``eta = h + B``.
+Every bathymetry function returns values on a 2^-22 grid (about 2.4e-7 in the
+units of the problem): such a bed is represented exactly by a single FP32
+value relative to any datum on the same grid within distance 4, so the FP32
+device and the FP64 oracle see the same bed.
 """
 from __future__ import annotations
 
@@ -35,6 +39,12 @@ from typing import Callable, List, Optional
 import numpy as np
 
 G_DEFAULT = 9.81
+BED_GRID = 2.0 ** -22
+
+
+def on_bed_grid(b):
+    """Round bed elevations to the 2^-22 grid."""
+    return np.rint(np.asarray(b, dtype=np.float64) / BED_GRID) * BED_GRID
 
 
 @dataclass
@@ -190,7 +200,7 @@ def beach_bathymetry(rng: np.random.Generator, n_bumps: int = 8, slope: float = 
         b = slope * x
         for k in range(n_bumps):
             b = b + amp * np.exp(-((x - cx[k]) ** 2 + (y - cy[k]) ** 2) / width ** 2)
-        return b
+        return on_bed_grid(b)
 
     return bath, (cx, cy)
 
@@ -220,7 +230,7 @@ def c3(n0: int = 54, seed: int = 3, n_bands: int = 4) -> Workload:
     L = float(n_bands)
 
     def bath(x, y):
-        return 0.9 * (np.asarray(x, dtype=np.float64) / L) ** 2
+        return on_bed_grid(0.9 * (np.asarray(x, dtype=np.float64) / L) ** 2)
 
     def init(x, y):
         x = np.asarray(x, dtype=np.float64)
@@ -255,7 +265,7 @@ def fourier_bathymetry(rng: np.random.Generator, n_modes: int = 16, amp: float =
     fmax = float(np.max(np.abs(f(gx, gy))))
 
     def bath(x, y):
-        return -mean_depth + amp * f(x, y) / fmax
+        return on_bed_grid(-mean_depth + amp * f(x, y) / fmax)
 
     return bath
 
@@ -288,13 +298,13 @@ def c5(n_inst: int = 64, seed: int = 5, kmin: float = 1e4, kmax: float = 2e5) ->
         cx, cy = rng.uniform(0.0, 1.0, size=2)
 
         def bath(x, y, slope=slope):
-            return slope * np.asarray(x, dtype=np.float64)
+            return on_bed_grid(slope * np.asarray(x, dtype=np.float64))
 
         def init(x, y, slope=slope, amp=amp, cx=cx, cy=cy):
             x = np.asarray(x, dtype=np.float64)
             y = np.asarray(y, dtype=np.float64)
             eta = 0.5 + amp * np.exp(-100.0 * ((x - cx) ** 2 + (y - cy) ** 2))
-            return np.maximum(0.0, eta - slope * x), _zeros_like(x), _zeros_like(x)
+            return np.maximum(0.0, eta - bath(x, y)), _zeros_like(x), _zeros_like(x)
 
         insts.append(Instance(vx, vy, etov, bath, init, f"c5[{i}] n={n}"))
     return Workload("c5", 3, insts, steps=200, cfl=0.2, seed=seed,
@@ -310,7 +320,7 @@ def lake_at_rest(n: int = 4, N: int = 3, jitter: float = 0.2, seed: int = 11,
     def bath(x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        return 0.2 * np.sin(2.0 * np.pi * x) * np.cos(np.pi * y) + 0.1 * x * y
+        return on_bed_grid(0.2 * np.sin(2.0 * np.pi * x) * np.cos(np.pi * y) + 0.1 * x * y)
 
     def init(x, y):
         return level - bath(x, y), _zeros_like(x), _zeros_like(x)
