@@ -436,6 +436,10 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
                 wred[size_t(st) * 64 + ln] = row == 0 ? wh[nd] : pmid[(row - 1) * Np + nd];
             }
     HIPCHECK(up(l.Wred, wred.data(), wred.size() * 8));
+    // the matrix-core kernel numbers face nodes by formula
+    for (size_t t = 0; t < re.fmask.size(); ++t)
+        if (re.fmask[t] != face_node_index(h->p.N, int(t)))
+            return fail(DG_EINVAL, "reference face nodes do not follow the row-by-row numbering");
     HIPCHECK(up(l.fmask, re.fmask.data(), re.fmask.size() * 4));
     HIPCHECK(up(l.nodeface, nodeface.data(), nodeface.size() * 4));
     HIPCHECK(up(l.wh, wh.data(), wh.size() * 8));
@@ -660,16 +664,14 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
         if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
     } else if (h->p.precision == DG_PLAIN_FP32) {
         a.mode = MODE_RHS_ONLY;
-        if (prof) HIPCHECK(hipEventRecord(ev->first, s));
-        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
-        if (prof) HIPCHECK(hipEventRecord(ev->second, s));
+        if (launch_step(a, s, 0, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
+            return fail(DG_EDEVICE, device_error_string());
         a.mode = MODE_UPDATE_ONLY;
         if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
     } else {
         a.mode = MODE_FUSED;
-        if (prof) HIPCHECK(hipEventRecord(ev->first, s));
-        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
-        if (prof) HIPCHECK(hipEventRecord(ev->second, s));
+        if (launch_step(a, s, 0, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
+            return fail(DG_EDEVICE, device_error_string());
     }
     if (h->p.limiter_mask & DG_LIMIT_TVB) {
         TvbArgs t = tvb_args(h, a);

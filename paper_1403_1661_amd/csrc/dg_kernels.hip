@@ -26,6 +26,7 @@
 // TVB kernel (one lane per element, FP64): characteristic minmod on the
 // edge-midpoint deviations against the neighbours' means, balancing, and the
 // depth rescaling of Eq. 5.3 (Section 5.3).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -474,8 +475,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 
 // ---------------------------------------------------------------------------
 // characteristic rows L of the flux Jacobian in direction (ex, ey) at a cell
-// mean (Section 5.3, Cockburn-Shu): shared by the in-kernel TVB screen and
-// the TVB kernel so both take the same decision
+// mean (Section 5.3, Cockburn-Shu), FP64
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void char_left(double hb, double mu, double mv, double g, double ex,
                                           double ey, double Lm[3][3]) {
@@ -486,6 +486,41 @@ __device__ __forceinline__ void char_left(double hb, double mu, double mv, doubl
     Lm[0][0] = (un + c) * i2c; Lm[0][1] = -ex * i2c; Lm[0][2] = -ey * i2c;
     Lm[1][0] = -ut;            Lm[1][1] = -ey;       Lm[1][2] = ex;
     Lm[2][0] = -(un - c) * i2c; Lm[2][1] = ex * i2c; Lm[2][2] = ey * i2c;
+}
+
+// Screen of the TVB keep test for one characteristic component: row r of L
+// at the mean (hb, mu, mv) in direction (ex, ey) applied to the midpoint
+// deviations (d0, d1, d2), in FP32 with the hardware reciprocal and square
+// root.  Returns true only if |a1| <= thr holds for the FP64 evaluation of
+// the same inputs: the FP32 result is widened by a bound of its rounding
+// error (unit roundoff u = 2^-24; inputs, rcp and sqrt within 2u, the row
+// within 16u (c + |ub| + |vb|) i2c, each product and sum within 2u), taken
+// with a factor 2 to spare.
+__device__ __forceinline__ bool tvb_screen_small(double hb, double mu, double mv, float g, float ex,
+                                                 float ey, int r, double d0, double d1, double d2,
+                                                 float thr) {
+    const float h = (float)hb;
+    const float ih = __builtin_amdgcn_rcpf(h);
+    const float ub = (float)mu * ih, vb = (float)mv * ih;
+    const float c = __builtin_amdgcn_sqrtf(g * h);
+    const float i2c = 0.5f * __builtin_amdgcn_rcpf(c);
+    const float un = ub * ex + vb * ey, ut = vb * ex - ub * ey;
+    float L0, L1, L2;
+    if (r == 1) {
+        L0 = -ut;
+        L1 = -ey;
+        L2 = ex;
+    } else {
+        const float sg = r == 0 ? -1.f : 1.f;
+        L0 = (c - sg * un) * i2c;
+        L1 = sg * ex * i2c;
+        L2 = sg * ey * i2c;
+    }
+    const float t0 = L0 * (float)d0, t1 = L1 * (float)d1, t2 = L2 * (float)d2;
+    const float a1 = t0 + t1 + t2;
+    const float err = 0x1p-19f * ((c + fabsf(ub) + fabsf(vb)) * (i2c + 1.f) * fabsf((float)d0) +
+                                  fabsf(t0) + fabsf(t1) + fabsf(t2));
+    return fabsf(a1) + err <= thr;
 }
 
 // ---------------------------------------------------------------------------
@@ -520,6 +555,14 @@ struct MShape {
     static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
 };
 
+// face node fn of the reference element from a 4-bit packed table (N <= 4)
+template <int N>
+__device__ __forceinline__ int face_node(int fn) {
+    static_assert(N <= 4, "3(N+1) face nodes of 4 bits must fit 64 bits");
+    constexpr unsigned long long bits = face_node_bits(N);
+    return (int)((bits >> (4 * fn)) & 15ull);
+}
+
 template <int KSP>
 __device__ __forceinline__ int kperm(int k) {
     // K index k is supplied by lane group k % 4 at step k / 4; each group's
@@ -549,71 +592,80 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     using S = MShape<N>;
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KT = S::KT, KS = S::KS, KB = S::KB;
     constexpr int KSP = S::KSP, RS = S::RS;
-    __shared__ __attribute__((aligned(16))) float sA[16][5][RS];
-    __shared__ double sVd[16][3][16];     // updated h, hu, hv per node (FP64)
-    __shared__ double sRed[16][16];       // 0 min h, 1-3 means, 4-12 deviations, 13-15 PP result
+    // LDS is per wave (its four elements): the X^T rows, and after they have
+    // been read into registers, the FP64 node values and reductions in the
+    // same bytes
+    struct WaveLds {
+        union {
+            float A[4][5][RS];
+            struct {
+                double Vd[4][3][16];   // updated h, hu, hv per node
+                double Red[4][16];     // 1-3 means, 4-12 deviations
+            } r;
+        };
+    };
+    __shared__ __attribute__((aligned(16))) WaveLds lds[4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, j = lane & 15;
     const int el = wave * 4 + q;
+    float (&sA)[4][5][RS] = lds[wave].A;
+    double (&sVd)[4][3][16] = lds[wave].r.Vd;
+    double (&sRed)[4][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int k = a.k_begin + blk * 16 + el;
     const bool live = k < a.k_end;
     const bool node = live && j < Np;
+    // loads are unconditional: lanes past the last element read the last
+    // element and lane 15 (j >= Np) reads node Np - 1; their results are
+    // never stored
+    const int kc = live ? k : a.k_end - 1;
     const unsigned KNp = (unsigned)a.KNp;
     const float g = a.g, hvel = a.hvel;
-    const unsigned idx = (unsigned)k * Np + j;
+    const unsigned idx = (unsigned)kc * Np + (j < Np ? j : Np - 1);
 
     // ---- independent global loads first
     LevelArgs L = a.lev[0];
-    if (MULTI && live) L = pick_level(a, level_of(a, k));
+    if (MULTI) L = pick_level(a, level_of(a, kc));
     const float* Qi = a.Q[L.parity];
-    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f, lo = 0.f;
+    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * kc);   // rx, ry, sx, sy
+    const float dtmin = ldg(a.geo, 16u * kc + 14u);
+    const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
+    const float eta = ldg(Qi, idx);
+    const float hu = ldg(Qi + KNp, idx);
+    const float hv = ldg(Qi + 2 * (size_t)KNp, idx);
+    const float lo = ldg(Qi + 3 * (size_t)KNp, idx);
+    const float Bn = ldg(a.B, idx);
     float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
-    float4 g0 = make_float4(0, 0, 0, 0);
-    float dtmin = 0.f;
-    int4 cn = make_int4(-1, -1, -1, 0);
+    if (L.ab[1] != 0.f) {
+        const float* R1 = a.R[L.slot[1]];
+        r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
+    }
+    if (L.ab[2] != 0.f) {
+        const float* R2 = a.R[L.slot[2]];
+        r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
+    }
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
     const int f = fn / Nfp, jj = fn - f * Nfp;
-    float nx = 0.f, ny = 0.f, fs = 0.f;
-    if (live) {
-        g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * k);
-        dtmin = ldg(a.geo, 16u * k + 14u);
-        cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)k);
-        if (j < Np) {
-            eta = ldg(Qi, idx);
-            hu = ldg(Qi + KNp, idx);
-            hv = ldg(Qi + 2 * (size_t)KNp, idx);
-            lo = ldg(Qi + 3 * (size_t)KNp, idx);
-            Bn = ldg(a.B, idx);
-            if (L.ab[1] != 0.f) {
-                const float* R1 = a.R[L.slot[1]];
-                r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
-            }
-            if (L.ab[2] != 0.f) {
-                const float* R2 = a.R[L.slot[2]];
-                r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
-            }
-        }
-        if (j < nF) {
-            nx = ldg(a.geo, 16u * k + 4u + f);
-            ny = ldg(a.geo, 16u * k + 7u + f);
-            fs = ldg(a.geo, 16u * k + 10u + f);
-        }
-    }
-    const int n = a.ops.fmask[fn];
+    const float nx = ldg(a.geo, 16u * kc + 4u + f);
+    const float ny = ldg(a.geo, 16u * kc + 7u + f);
+    const float fs = ldg(a.geo, 16u * kc + 10u + f);
+    const int n = face_node<N>(fn);
     const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
-    float etaP = 0.f, huP = 0.f, hvP = 0.f, BP = 0.f, loP = 0.f;
-    if (fnode && nb >= 0) {
-        const int f2 = (cn.w >> (2 * f)) & 3;
-        const unsigned id2 = (unsigned)nb * Np + a.ops.fmask[f2 * Nfp + (Nfp - 1 - jj)];
-        BP = ldg(a.B, id2);
+    // exterior node: node Nfp-1-jj of the neighbour's face f2 (a wall face
+    // reads its own face here and is replaced by the mirror state below)
+    const int f2 = nb >= 0 ? (cn.w >> (2 * f)) & 3 : f;
+    const int nbc = nb >= 0 ? nb : kc;
+    const unsigned id2 = (unsigned)nbc * Np + face_node<N>(f2 * Nfp + (Nfp - 1 - jj));
+    float BP = ldg(a.B, id2);
+    float etaP, huP, hvP, loP = 0.f;
+    {
         const float* Q2 = Qi;
         bool from_half = false;
         if (MULTI) {
-            const LevelArgs L2 = pick_level(a, level_of(a, nb));
+            const LevelArgs L2 = pick_level(a, level_of(a, nbc));
             Q2 = a.Q[L2.parity];
             from_half = !L2.active && a.half != nullptr;
         }
@@ -623,7 +675,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             hvP = ldg(Q2 + 2 * (size_t)KNp, id2);
             loP = ldg(Q2 + 3 * (size_t)KNp, id2);
         } else {
-            const unsigned hid = (unsigned)nb * nF + f2 * Nfp + (Nfp - 1 - jj);
+            const unsigned hid = (unsigned)nbc * nF + f2 * Nfp + (Nfp - 1 - jj);
             const unsigned KnF = (unsigned)a.KnF;
             etaP = ldg(a.half, hid);
             huP = ldg(a.half + KnF, hid);
@@ -653,22 +705,22 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sA[el][c][kperm<KSP>(j)] = -(rx * F[c] + ry * G[c]);
-            sA[el][c][kperm<KSP>(Np + j)] = -(sx * F[c] + sy * G[c]);
+            sA[q][c][kperm<KSP>(j)] = -(rx * F[c] + ry * G[c]);
+            sA[q][c][kperm<KSP>(Np + j)] = -(sx * F[c] + sy * G[c]);
         }
         const float bb = Bn - B0;
-        sA[el][3][kperm<KSP>(j)] = rx * bb;
-        sA[el][3][kperm<KSP>(Np + j)] = sx * bb;
-        sA[el][4][kperm<KSP>(j)] = ry * bb;
-        sA[el][4][kperm<KSP>(Np + j)] = sy * bb;
+        sA[q][3][kperm<KSP>(j)] = rx * bb;
+        sA[q][3][kperm<KSP>(Np + j)] = sx * bb;
+        sA[q][4][kperm<KSP>(j)] = ry * bb;
+        sA[q][4][kperm<KSP>(Np + j)] = sy * bb;
     }
     if (j < nF) {   // lift columns of the bed rows are zero
-        sA[el][3][kperm<KSP>(2 * Np + j)] = 0.f;
-        sA[el][4][kperm<KSP>(2 * Np + j)] = 0.f;
+        sA[q][3][kperm<KSP>(2 * Np + j)] = 0.f;
+        sA[q][4][kperm<KSP>(2 * Np + j)] = 0.f;
     }
     if (j < 4 * KSP - KT) {   // K padding of all rows
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sA[el][c][kperm<KSP>(KT + j)] = 0.f;
+        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(KT + j)] = 0.f;
     }
 
     // ---- face node fn = j of element q: reconstructed states, LLF flux
@@ -677,7 +729,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const float hvM = __shfl(hv, (lane & ~15) + n);
     const float BM = __shfl(Bn, (lane & ~15) + n);
     const float loM = __shfl(lo, (lane & ~15) + n);
-    if (fnode && nb < 0) {
+    if (nb < 0) {
         const float mn = huM * nx + hvM * ny;
         etaP = etaM;
         loP = loM;
@@ -706,21 +758,20 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         const float au = hsM * uM * unM + hsP * uP * unP;
         const float av = hsM * vM * unM + hsP * vP * unP;
         const int kp = kperm<KSP>(2 * Np + fn);
-        sA[el][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
-        sA[el][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
-        sA[el][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
+        sA[q][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
+        sA[q][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
+        sA[q][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
     }
     wave_lds_sync();
 
     // ---- contraction on the matrix cores
     const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
     const int ag = lane >> 4;           // K group supplied by this lane
-    const int eA = wave * 4 + (ar >> 2);
     float av[KSP], ay[KSP];
 #pragma unroll
     for (int s4 = 0; s4 < KSP / 4; ++s4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(&sA[eA][ar & 3][ag * KSP + 4 * s4]);
-        const float4 y4 = *reinterpret_cast<const float4*>(&sA[eA][4][ag * KSP + 4 * s4]);
+        const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][ar & 3][ag * KSP + 4 * s4]);
+        const float4 y4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][4][ag * KSP + 4 * s4]);
         av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
         ay[4 * s4] = y4.x; ay[4 * s4 + 1] = y4.y; ay[4 * s4 + 2] = y4.z; ay[4 * s4 + 3] = y4.w;
     }
@@ -768,9 +819,10 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     }
     // ---- FP64 element reductions on the matrix cores, min depth by shuffles
     const double h64 = node ? (double)qn[0] - (double)Bn + (double)qlo : 0.0;
-    sVd[el][0][j] = h64;
-    sVd[el][1][j] = node ? (double)qn[1] : 0.0;
-    sVd[el][2][j] = node ? (double)qn[2] : 0.0;
+    wave_lds_sync();   // X^T reads done before the node values overwrite them
+    sVd[q][0][j] = h64;
+    sVd[q][1][j] = node ? (double)qn[1] : 0.0;
+    sVd[q][2][j] = node ? (double)qn[2] : 0.0;
     double hmin = node ? h64 : 1e300;
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, 16));
@@ -778,63 +830,53 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
         const int c = lane & 15;          // column: element c/4, field c%4
-        const int ec = wave * 4 + (c >> 2), fc = c & 3;
+        const int fc = c & 3;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const double bv = fc < 3 ? sVd[ec][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
+            const double bv = fc < 3 ? sVd[c >> 2][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
             red = __builtin_amdgcn_mfma_f64_16x16x4f64(wred[s], bv, red, 0, 0, 0);
         }
         // lane 16 g + c holds row g (0: mean, 1-3: midpoint deviation g-1) of column c
-        if (fc < 3) sRed[ec][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
+        if (fc < 3) sRed[c >> 2][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
     }
-    if (j == 0) sRed[el][0] = hmin;
     wave_lds_sync();
-    // ---- positivity limiter decision (Algorithm 5.2)
-    if (live && j == 0) {
-        const double hb = sRed[el][1];
-        double scale = 1.0, hdry = 0.0;
-        int code = 0;
-        if (a.pp_on && hmin <= (double)a.eps) {
-            if (hb < (double)a.h0) {
-                code = 2;
-                if (hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
-                hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);
-                scale = 0.0;
-            } else {
-                code = 1;
-                const double d0 = sRed[el][4], d1 = sRed[el][5], d2 = sRed[el][6];
-                const double Ssum = d0 + d1 + d2;
-                const double vmin = hb + fmin(Ssum - 2.0 * d0, fmin(Ssum - 2.0 * d1, Ssum - 2.0 * d2));
-                const double den = hb - vmin;
-                scale = den > 0.0 ? fmin(1.0, (hb - (double)a.h0) / den) : 1.0;
-            }
+    // ---- positivity limiter decision (Algorithm 5.2), taken by all lanes of
+    // the element (hmin is already the element minimum in every lane)
+    const double hb = sRed[q][1];
+    double scale = 1.0, hdry = 0.0;
+    int code = 0;
+    if (a.pp_on && hmin <= (double)a.eps) {
+        if (hb < (double)a.h0) {
+            code = 2;
+            hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);
+            scale = 0.0;
+        } else {
+            code = 1;
+            const double d0 = sRed[q][4], d1 = sRed[q][5], d2 = sRed[q][6];
+            const double Ssum = d0 + d1 + d2;
+            const double vmin = hb + fmin(Ssum - 2.0 * d0, fmin(Ssum - 2.0 * d1, Ssum - 2.0 * d2));
+            const double den = hb - vmin;
+            scale = den > 0.0 ? fmin(1.0, (hb - (double)a.h0) / den) : 1.0;
         }
-        sRed[el][13] = (double)code;
-        sRed[el][14] = scale;
-        sRed[el][15] = hdry;
     }
-    wave_lds_sync();
-    const int code = (int)sRed[el][13];
-    const double scale = sRed[el][14], hdry = sRed[el][15];
+    if (live && j == 0 && code == 2 && hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
     // post-limiter means
-    const double mean0 = code == 2 ? hdry : sRed[el][1];
-    const double mean1 = code == 2 ? 0.0 : sRed[el][2];
-    const double mean2 = code == 2 ? 0.0 : sRed[el][3];
-    // ---- TVB screen: lane j < 9 checks component j % 3 of edge j / 3
+    const double mean0 = code == 2 ? hdry : hb;
+    const double mean1 = code == 2 ? 0.0 : sRed[q][2];
+    const double mean2 = code == 2 ? 0.0 : sRed[q][3];
+    // ---- TVB screen: lane j < 9 checks component j % 3 of edge j / 3 in FP32
+    // with a bound on its rounding error, so an element leaves the candidate
+    // set only when the FP64 test would keep every component too
     bool small = true;
     double devw = 0.0;
     if (live && j < 9) {
         const int ed = j / 3, r = j % 3;
-        devw = scale * sRed[el][4 + 3 * r + ed];   // deviation of field r at edge ed
+        devw = scale * sRed[q][4 + 3 * r + ed];   // deviation of field r at edge ed
         if (a.tvb_on && code != 2) {
             const float* st = a.stencil + 16u * k;
-            double Lm[3][3];
-            char_left(mean0, mean1, mean2, (double)g, (double)st[4 * ed + 2], (double)st[4 * ed + 3], Lm);
-            const double d0 = scale * sRed[el][4 + ed];
-            const double d1 = scale * sRed[el][7 + ed];
-            const double d2 = scale * sRed[el][10 + ed];
-            const double a1 = Lm[r][0] * d0 + Lm[r][1] * d1 + Lm[r][2] * d2;
-            small = fabs(a1) <= (double)st[12];
+            small = tvb_screen_small(mean0, mean1, mean2, g, st[4 * ed + 2], st[4 * ed + 3], r,
+                                     scale * sRed[q][4 + ed], scale * sRed[q][7 + ed],
+                                     scale * sRed[q][10 + ed], st[12]);
         }
     }
     const unsigned long long bal = __ballot(small);
@@ -853,9 +895,9 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     } else if (code == 1) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double val = sRed[el][1 + c];
+            double val = sRed[q][1 + c];
 #pragma unroll
-            for (int ed = 0; ed < 3; ++ed) val += scale * sRed[el][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
+            for (int ed = 0; ed < 3; ++ed) val += scale * sRed[q][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
             if (c == 0)
                 eta_split(val + (double)Bn, out[0], olo);
             else
@@ -870,127 +912,129 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// TVB limiter with the positivity modification of Eq. 5.3, one lane per element
+// TVB limiter with the positivity modification of Eq. 5.3 (Section 5.3),
+// FP64.  Four lanes per element: lane t < 3 owns edge t (its neighbour t,
+// its stencil row, its characteristic decomposition); the balancing and the
+// P1 output are shared by the quad (lane t writes nodes t, t+4, ...).
+// Neighbour flags are read while neighbours rewrite theirs, which is safe:
+// a rewrite keeps the positivity bits (0-1), the only bits read here.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
-    const int k = a.k_begin + blockIdx.x * 256 + threadIdx.x;
-    if (k >= a.k_end) return;
+    const int tid = threadIdx.x;
+    const int t = tid & 3;
+    const int lane = tid & 63, qb4 = lane & ~3;
+    const int k = a.k_begin + blockIdx.x * 64 + (tid >> 2);
+    if (k >= a.k_end) return;   // the whole quad leaves together
     const unsigned K = (unsigned)a.K;
+    const int ed = t < 3 ? t : 0;   // lane 3 shadows edge 0 and is ignored
     // round 1: everything indexed by k alone
     const uint8_t fl = a.flags[k];
     const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)k);
     const uint8_t pp = fl & 3;
     if (pp == 2) {
-        a.flags[k] = pp;
+        if (t == 0) a.flags[k] = pp;
         return;
     }
     const bool cand = (fl & kTvbCandidate) != 0;
     double qb[3] = {0.0, 0.0, 0.0};
-    double dev[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    float st[16];
+    double dev[3] = {0.0, 0.0, 0.0};   // field c at edge ed
+    float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
+    float M2 = 0.f;
+    int pairs = 0;
     if (cand) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) qb[c] = ldg(a.means, c * K + k);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) dev[c] = ldg(a.devs, (3 * c + ed) * K + k);
+        st = ldg(reinterpret_cast<const float4*>(a.stencil), 4u * k + ed);   // alpha_j, alpha_k, ex, ey
+        const float2 mp = ldg(reinterpret_cast<const float2*>(a.stencil), 8u * k + 6u);
+        M2 = mp.x;
+        pairs = __float_as_int(mp.y);
+    }
+    // round 2: neighbour t (flag, and means for candidates)
+    const int nbt = t == 0 ? cn.x : (t == 1 ? cn.y : (t == 2 ? cn.z : -1));
+    bool dry_t = false;
+    double nm[3] = {0.0, 0.0, 0.0};
+    if (nbt >= 0) {
+        dry_t = (a.flags[nbt] & 3) == 2;
+        if (cand) {
 #pragma unroll
-            for (int ed = 0; ed < 3; ++ed) dev[c][ed] = ldg(a.devs, (3 * c + ed) * K + k);
-        const float4* s4 = reinterpret_cast<const float4*>(a.stencil) + 4u * k;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float4 v = s4[t];
-            st[4 * t] = v.x; st[4 * t + 1] = v.y; st[4 * t + 2] = v.z; st[4 * t + 3] = v.w;
+            for (int c = 0; c < 3; ++c) nm[c] = ldg(a.means, c * K + (unsigned)nbt);
         }
     }
-    // round 2: neighbours (flags, and means for candidates)
-    const int nbs[3] = {cn.x, cn.y, cn.z};
-    bool nb_dry = false;
-    double nbm[3][3];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const int nb = nbs[f];
-        if (nb >= 0) {
-            nb_dry = nb_dry || ((a.flags[nb] & 3) == 2);
-            if (cand) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) nbm[f][c] = ldg(a.means, c * K + (unsigned)nb);
-            }
-        }
-    }
-    if (nb_dry) {
-        a.flags[k] = pp;
+    if (((__ballot(dry_t) >> qb4) & 0xFull) != 0) {   // a face neighbour is dry: skipped
+        if (t == 0) a.flags[k] = pp;
         return;
     }
     if (!cand) {   // every characteristic increment within M d^2
-        a.flags[k] = pp | (1 << 2);
+        if (t == 0) a.flags[k] = pp | (1 << 2);
         return;
     }
-    const float* gk = a.geo + 16LL * k;
-    double diff[3][3];   // [face][field]
+    // mean difference across face t (a wall mirrors the momentum mean)
+    double df[3] = {0.0, 0.0, 0.0};
+    if (nbt < 0 && t < 3) {
+        const float* gk = a.geo + 16LL * k;
+        const double nx = gk[4 + ed], ny = gk[7 + ed];
+        const double mn = qb[1] * nx + qb[2] * ny;
+        df[0] = 0.0;
+        df[1] = -2.0 * mn * nx;
+        df[2] = -2.0 * mn * ny;
+    } else if (nbt >= 0) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        if (nbs[f] < 0) {
-            const double nx = gk[4 + f], ny = gk[7 + f];
-            const double mn = qb[1] * nx + qb[2] * ny;
-            diff[f][0] = 0.0;
-            diff[f][1] = -2.0 * mn * nx;
-            diff[f][2] = -2.0 * mn * ny;
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) diff[f][c] = nbm[f][c] - qb[c];
-        }
+        for (int c = 0; c < 3; ++c) df[c] = nm[c] - qb[c];
     }
-    const int pairs = __float_as_int(st[13]);
-    const double M2 = st[12];
+    // edge ed: neighbour-mean increment from the faces of its stencil pair
+    const int pj = (pairs >> (4 * ed)) & 3, pk = (pairs >> (4 * ed + 2)) & 3;
+    double dbar[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        dbar[c] = (double)st.x * __shfl(df[c], qb4 + pj) + (double)st.y * __shfl(df[c], qb4 + pk);
     const double hb = qb[0];
     const double ub = qb[1] / hb, vb = qb[2] / hb;
-    const double c = sqrt(a.g * hb);
-    double D[3][3];   // [field][edge]
+    const double cc = sqrt(a.g * hb);
+    const double ex = st.z, ey = st.w;
+    double Lm[3][3];
+    char_left(qb[0], qb[1], qb[2], a.g, ex, ey, Lm);
+    const double Rm[3][3] = {{1.0, 0.0, 1.0},
+                             {ub - cc * ex, -ey, ub + cc * ex},
+                             {vb - cc * ey, ex, vb + cc * ey}};
+    double mt[3];
     bool all_a1 = true;
 #pragma unroll
-    for (int ed = 0; ed < 3; ++ed) {
-        const int pj = (pairs >> (4 * ed)) & 3, pk = (pairs >> (4 * ed + 2)) & 3;
-        const double aj = st[4 * ed], ak = st[4 * ed + 1];
-        const double ex = st[4 * ed + 2], ey = st[4 * ed + 3];
-        double dbar[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) dbar[q] = aj * diff[pj][q] + ak * diff[pk][q];
-        double Lm[3][3];
-        char_left(qb[0], qb[1], qb[2], a.g, ex, ey, Lm);
-        const double Rm[3][3] = {{1.0, 0.0, 1.0},
-                                 {ub - c * ex, -ey, ub + c * ex},
-                                 {vb - c * ey, ex, vb + c * ey}};
-        double mt[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const double a1 = Lm[r][0] * dev[0][ed] + Lm[r][1] * dev[1][ed] + Lm[r][2] * dev[2][ed];
-            const double a2 = a.nu * (Lm[r][0] * dbar[0] + Lm[r][1] * dbar[1] + Lm[r][2] * dbar[2]);
-            const bool small = fabs(a1) <= M2;
-            const bool same = (a1 > 0.0 && a2 > 0.0) || (a1 < 0.0 && a2 < 0.0);
-            const double mm = same ? copysign(fmin(fabs(a1), fabs(a2)), a1) : 0.0;
-            mt[r] = small ? a1 : mm;
-            all_a1 = all_a1 && (small || a1 == 0.0 || (same && fabs(a1) <= fabs(a2)));
-        }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) D[q][ed] = Rm[q][0] * mt[0] + Rm[q][1] * mt[1] + Rm[q][2] * mt[2];
+    for (int r = 0; r < 3; ++r) {
+        const double a1 = Lm[r][0] * dev[0] + Lm[r][1] * dev[1] + Lm[r][2] * dev[2];
+        const double a2 = a.nu * (Lm[r][0] * dbar[0] + Lm[r][1] * dbar[1] + Lm[r][2] * dbar[2]);
+        const bool small = fabs(a1) <= (double)M2;
+        const bool same = (a1 > 0.0 && a2 > 0.0) || (a1 < 0.0 && a2 < 0.0);
+        const double mm = same ? copysign(fmin(fabs(a1), fabs(a2)), a1) : 0.0;
+        mt[r] = small ? a1 : mm;
+        all_a1 = all_a1 && (small || a1 == 0.0 || (same && fabs(a1) <= fabs(a2)));
     }
-    if (all_a1) {
-        a.flags[k] = pp | (1 << 2);
+    if (((__ballot(!all_a1 && t < 3) >> qb4) & 0xFull) == 0) {   // nothing limited: keep P^N
+        if (t == 0) a.flags[k] = pp | (1 << 2);
         return;
     }
+    double Dl[3];   // increments of edge ed in conserved variables
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Dl[q] = Rm[q][0] * mt[0] + Rm[q][1] * mt[1] + Rm[q][2] * mt[2];
+    double D[3][3];   // [field][edge], gathered by every lane of the quad
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) D[q][e] = __shfl(Dl[q], qb4 + e);
     // balance each conserved component
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double pos = 0.0, neg = 0.0;
 #pragma unroll
-        for (int ed = 0; ed < 3; ++ed) {
-            pos += fmax(D[q][ed], 0.0);
-            neg += fmax(-D[q][ed], 0.0);
+        for (int e = 0; e < 3; ++e) {
+            pos += fmax(D[q][e], 0.0);
+            neg += fmax(-D[q][e], 0.0);
         }
         const double thp = pos > 0.0 ? fmin(1.0, neg / pos) : 1.0;
         const double thm = neg > 0.0 ? fmin(1.0, pos / neg) : 1.0;
 #pragma unroll
-        for (int ed = 0; ed < 3; ++ed) D[q][ed] = thp * fmax(D[q][ed], 0.0) - thm * fmax(-D[q][ed], 0.0);
+        for (int e = 0; e < 3; ++e) D[q][e] = thp * fmax(D[q][e], 0.0) - thm * fmax(-D[q][e], 0.0);
     }
     // Eq. 5.3 on the depth increments
     int code = 2;
@@ -1003,18 +1047,15 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
             double th = den > 0.0 ? (hb + dbh - a.h0) / den : 0.0;
             th = fmin(1.0, fmax(0.0, th));
 #pragma unroll
-            for (int ed = 0; ed < 3; ++ed) D[0][ed] = dbh + th * (D[0][ed] - dbh);
+            for (int e = 0; e < 3; ++e) D[0][e] = dbh + th * (D[0][e] - dbh);
             code = 3;
         }
     }
-    // P1 output: mean + sum_i D_i phi_i at every node
-    int l = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxLevels - 1; ++q) l += (q + 1 < a.nlev && k >= a.lev[q].end) ? 1 : 0;
-    const LevelArgs L = pick_level(a, l);
+    // P1 output: mean + sum_i D_i phi_i, nodes t, t+4, ... of the element
+    const LevelArgs L = pick_level(a, level_of(a, k));
     float* Qo = a.Q[1 - L.parity];
     const int Np = a.Np;
-    for (int j = 0; j < Np; ++j) {
+    for (int j = t; j < Np; j += 4) {
         const double p0 = a.phi[j], p1 = a.phi[Np + j], p2 = a.phi[2 * Np + j];
         const long long id = (long long)k * Np + j;
         const double hval = qb[0] + D[0][0] * p0 + D[0][1] * p1 + D[0][2] * p2;
@@ -1025,7 +1066,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         Qo[a.KNp + id] = (float)(qb[1] + D[1][0] * p0 + D[1][1] * p1 + D[1][2] * p2);
         Qo[2 * a.KNp + id] = (float)(qb[2] + D[2][0] * p0 + D[2][1] * p1 + D[2][2] * p2);
     }
-    a.flags[k] = pp | (code << 2);
+    if (t == 0) a.flags[k] = pp | (code << 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1105,22 +1146,31 @@ int step_elems_per_block(int N, int engine) {
     return 256 / Np;
 }
 
+// kernel launch; with a start/stop event pair the events take the kernel's
+// own start and end timestamps from its dispatch (no queue or launch gaps)
+template <typename K>
+static void dispatch(K kernel, int blocks, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
+    if (e0 != nullptr)
+        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a);
+}
+
 template <int N>
-static int launch_step_n(const StepArgs& a, hipStream_t s) {
+static int launch_step_n(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
     if constexpr (N <= 4) {
         if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_FUSED) {
             if (a.nlev > 1)
-                hipLaunchKernelGGL((step_mfma_kernel<N, true>), dim3((n + 15) / 16), dim3(256), 0, s, a);
+                dispatch(step_mfma_kernel<N, true>, (n + 15) / 16, s, a, e0, e1);
             else
-                hipLaunchKernelGGL((step_mfma_kernel<N, false>), dim3((n + 15) / 16), dim3(256), 0, s, a);
+                dispatch(step_mfma_kernel<N, false>, (n + 15) / 16, s, a, e0, e1);
             return check_launch("step mfma kernel");
         }
     }
     const int E = Shape<N>::E;
-    const int blocks = (n + E - 1) / E;
-    hipLaunchKernelGGL(step_kernel<N>, dim3(blocks), dim3(256), 0, s, a);
+    dispatch(step_kernel<N>, (n + E - 1) / E, s, a, e0, e1);
     return check_launch("step kernel");
 }
 
@@ -1129,16 +1179,17 @@ int mfma_steps(int N) {
     return (2 * Np + nF + 3) / 4;
 }
 
-int launch_step(const StepArgs& a, void* stream, int elems_per_block) {
+int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_start, void* ev_stop) {
     (void)elems_per_block;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = static_cast<hipEvent_t>(ev_start), e1 = static_cast<hipEvent_t>(ev_stop);
     switch (a.N) {
-        case 1: return launch_step_n<1>(a, s);
-        case 2: return launch_step_n<2>(a, s);
-        case 3: return launch_step_n<3>(a, s);
-        case 4: return launch_step_n<4>(a, s);
-        case 5: return launch_step_n<5>(a, s);
-        case 6: return launch_step_n<6>(a, s);
+        case 1: return launch_step_n<1>(a, s, e0, e1);
+        case 2: return launch_step_n<2>(a, s, e0, e1);
+        case 3: return launch_step_n<3>(a, s, e0, e1);
+        case 4: return launch_step_n<4>(a, s, e0, e1);
+        case 5: return launch_step_n<5>(a, s, e0, e1);
+        case 6: return launch_step_n<6>(a, s, e0, e1);
         default:
             std::snprintf(g_dev_err, sizeof(g_dev_err), "unsupported N=%d", a.N);
             return -1;
@@ -1148,7 +1199,7 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block) {
 int launch_tvb(const TvbArgs& a, void* stream) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(tvb_kernel, dim3((n + 255) / 256), dim3(256), 0,
+    hipLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0,
                        static_cast<hipStream_t>(stream), a);
     return check_launch("tvb kernel");
 }

@@ -12,6 +12,24 @@ constexpr int kMaxLevels = 6;
 // (not dry, and some characteristic midpoint increment exceeds M d^2)
 constexpr int kTvbCandidate = 16;
 
+// Face node fn = f (N+1) + p of the reference triangle (faces s = -1, r + s
+// = 0, r = -1, each in counter-clockwise order) for nodes numbered row by row
+// in s, row j holding N+1-j nodes in increasing r.  The host checks its face
+// masks against this numbering when it binds.
+constexpr int face_node_index(int N, int fn) {
+    const int Nfp = N + 1, f = fn / Nfp, p = fn % Nfp;
+    const int i = f == 0 ? p : (f == 1 ? N - p : 0);   // r index
+    const int j = f == 0 ? 0 : (f == 1 ? p : N - p);   // s index
+    return j * (N + 1) - j * (j - 1) / 2 + i;
+}
+
+// all 3(N+1) face nodes packed 4 bits each (N <= 4)
+constexpr unsigned long long face_node_bits(int N) {
+    unsigned long long b = 0;
+    for (int fn = 0; fn < 3 * (N + 1); ++fn) b |= (unsigned long long)face_node_index(N, fn) << (4 * fn);
+    return b;
+}
+
 // Kernel modes of the step kernel.
 enum StepMode : int {
     MODE_FUSED = 0,        // RHS + AB update + positivity limiter + means/deviations
@@ -106,7 +124,9 @@ struct DiagArgs {
     double* out;           // [16]
 };
 
-int launch_step(const StepArgs& a, void* stream, int elems_per_block);
+// ev_start / ev_stop (hipEvent_t, optional): timestamps of the kernel itself
+int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_start = nullptr,
+                void* ev_stop = nullptr);
 int launch_tvb(const TvbArgs& a, void* stream);
 int launch_diag(const DiagArgs& a, void* stream);
 int step_elems_per_block(int N, int engine);
