@@ -165,6 +165,17 @@ int32_t dg_prepare(dg_solver* h, void* stream);
  * Errors: DG_ENOTBOUND (state not set), DG_EDEVICE. */
 int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 
+/* Autotuner (launch shape of the step kernel).  Times the step kernel of
+ * the next tick `reps` times for each elements-per-block candidate of the
+ * path (matrix-core path: 4, 8 and 16; the VALU paths have one shape) and
+ * keeps the fastest in the solver's parameters.  The state, history, flags
+ * and counters are left as they were.  Writes min(max_out, candidates) pairs (elements per
+ * block, average microseconds) to epb/us and the candidate count to *n_out.
+ * Synchronises `stream`.  Needs a prepared state (dg_prepare or an earlier
+ * dg_advance).  Errors: DG_EINVAL, DG_ENOTBOUND, DG_EDEVICE. */
+int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out, int32_t* epb,
+                    double* us, void* stream);
+
 /* Current state of instance `inst` as FP64 depth and momenta ([K][Np]).
  * On the device the surface level is an FP32 pair hi + lo (relative to a
  * per-instance datum) and the momenta are FP32.  Synchronises `stream`. */

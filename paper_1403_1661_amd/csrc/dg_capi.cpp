@@ -183,6 +183,15 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         return fail(DG_EINVAL, "the BF16 split contraction is not available in this build");
     if (p->precision == DG_FUSED_MFMA32 && p->N > 4)
         return fail(DG_EINVAL, "the MFMA contraction needs Np <= 16 (N <= 4)");
+    if (p->elems_per_block != 0) {
+        const bool mfma = p->precision == DG_FUSED_MFMA32;
+        const int valu_e = 256 / ((p->N + 1) * (p->N + 2) / 2);
+        const bool ok = mfma ? (p->elems_per_block == 4 || p->elems_per_block == 8 || p->elems_per_block == 16)
+                             : p->elems_per_block == valu_e;
+        if (!ok)
+            return fail(DG_EINVAL, mfma ? "elems_per_block must be 0, 4, 8 or 16 on the MFMA path"
+                                        : "elems_per_block must be 0 or floor(256 / Np) on the VALU paths");
+    }
     std::unique_ptr<dg_solver> h;
     try {
         h.reset(new dg_solver());
@@ -405,16 +414,16 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     // Op[node l % 16][K index 4 s + l / 16] (0 outside Np x (2Np + 3Nfp))
     std::vector<float> amfma;
     if (h->p.N <= 4) {
-        const int KT = 2 * Np + nF, KS = mfma_steps(h->p.N);
+        const int KV = mfma_kv(h->p.N), KS = mfma_steps(h->p.N);
         amfma.assign(size_t(KS) * 64, 0.f);
         for (int st = 0; st < KS; ++st)
             for (int ln = 0; ln < 64; ++ln) {
                 const int node = ln % 16, kk = 4 * st + ln / 16;
-                if (node >= Np || kk >= KT) continue;
-                double v;
+                if (node >= Np) continue;
+                double v = 0.0;
                 if (kk < Np) v = re.Dr(node, kk);
                 else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
-                else v = re.LIFT(node, kk - 2 * Np);
+                else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
                 amfma[size_t(st) * 64 + ln] = float(v);
             }
     }
@@ -582,8 +591,6 @@ static StepArgs base_step_args(dg_solver* h) {
     a.ops.pmid = reinterpret_cast<const double*>(h->ws + l.pmid);
     a.ops.phi = reinterpret_cast<const double*>(h->ws + l.phi);
     a.ops.Wred = reinterpret_cast<const double*>(h->ws + l.Wred);
-    a.stencil = reinterpret_cast<const float*>(h->ws + l.stencil);
-    a.tvb_on = (h->p.limiter_mask & DG_LIMIT_TVB) ? 1 : 0;
     a.g = float(h->p.g);
     a.h0 = float(h->p.h0);
     a.eps = float(h->p.eps);
@@ -661,16 +668,16 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
     }
     if (limit_only) {
         a.mode = MODE_LIMIT_ONLY;
-        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+        if (launch_step(a, s, h->p.elems_per_block)) return fail(DG_EDEVICE, device_error_string());
     } else if (h->p.precision == DG_PLAIN_FP32) {
         a.mode = MODE_RHS_ONLY;
-        if (launch_step(a, s, 0, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
+        if (launch_step(a, s, h->p.elems_per_block, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
             return fail(DG_EDEVICE, device_error_string());
         a.mode = MODE_UPDATE_ONLY;
-        if (launch_step(a, s, 0)) return fail(DG_EDEVICE, device_error_string());
+        if (launch_step(a, s, h->p.elems_per_block)) return fail(DG_EDEVICE, device_error_string());
     } else {
         a.mode = MODE_FUSED;
-        if (launch_step(a, s, 0, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
+        if (launch_step(a, s, h->p.elems_per_block, prof ? ev->first : nullptr, prof ? ev->second : nullptr))
             return fail(DG_EDEVICE, device_error_string());
     }
     if (h->p.limiter_mask & DG_LIMIT_TVB) {
@@ -811,6 +818,84 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
         if (rc) return rc;
         --n_steps;
     }
+    return DG_OK;
+}
+
+int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out, int32_t* epb_out,
+                    double* us_out, void* stream) {
+    if (!h || !n_out || (max_out > 0 && (!epb_out || !us_out))) return fail(DG_EINVAL, "bad argument");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "prepare the state (dg_prepare) before tuning");
+    if (reps < 1) reps = 10;
+    HIPCHECK(hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int> cand;
+    if (h->p.precision == DG_FUSED_MFMA32)
+        cand = {4, 8, 16};
+    else
+        cand = {step_elems_per_block(h->p.N, engine_of(h->p.precision))};
+    // The trial launches repeat the step kernel of the next tick (tick 0 of
+    // the next coarse step, all levels active): they rewrite the buffers that
+    // tick rewrites with the same values, except the flag bytes (which the TVB
+    // pass has completed) and the negative-mean counter, saved and restored.
+    HIPCHECK(hipStreamSynchronize(s));
+    const Layout& l = h->lay;
+    std::vector<uint8_t> flags(size_t(h->K));
+    unsigned long long counter = 0;
+    HIPCHECK(hipMemcpy(flags.data(), h->ws + l.flags, flags.size(), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(&counter, h->ws + l.counters, 8, hipMemcpyDeviceToHost));
+    StepArgs a = base_step_args(h);
+    fill_levels(h, a.lev, h->L, false);
+    a.k_begin = 0;
+    a.k_end = h->lev_end[h->L - 1];
+    a.mode = h->p.precision == DG_PLAIN_FP32 ? MODE_RHS_ONLY : MODE_FUSED;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    int best = cand[0];
+    double best_us = 1e300;
+    int n = 0;
+    int rc = DG_OK;
+    for (int c : cand) {
+        double tot = 0.0;
+        for (int w = 0; w < 2 && rc == DG_OK; ++w)
+            if (launch_step(a, s, c)) rc = fail(DG_EDEVICE, device_error_string());
+        for (int r = 0; r < reps && rc == DG_OK; ++r) {
+            if (launch_step(a, s, c, e0, e1)) {
+                rc = fail(DG_EDEVICE, device_error_string());
+                break;
+            }
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(DG_EDEVICE, "event timing failed");
+                break;
+            }
+            tot += ms;
+        }
+        if (rc != DG_OK) break;
+        const double us = 1000.0 * tot / reps;
+        if (n < max_out) {
+            epb_out[n] = c;
+            us_out[n] = us;
+        }
+        ++n;
+        if (us < best_us) {
+            best_us = us;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DG_OK) return rc;
+    HIPCHECK(hipStreamSynchronize(s));
+    HIPCHECK(hipMemcpy(h->ws + l.flags, flags.data(), flags.size(), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.counters, &counter, 8, hipMemcpyHostToDevice));
+    h->p.elems_per_block = best;
+    if (h->graph) {   // captured launches carry the old block shape
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+        h->have_graph = false;
+    }
+    *n_out = n;
     return DG_OK;
 }
 

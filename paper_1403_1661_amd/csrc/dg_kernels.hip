@@ -488,41 +488,6 @@ __device__ __forceinline__ void char_left(double hb, double mu, double mv, doubl
     Lm[2][0] = -(un - c) * i2c; Lm[2][1] = ex * i2c; Lm[2][2] = ey * i2c;
 }
 
-// Screen of the TVB keep test for one characteristic component: row r of L
-// at the mean (hb, mu, mv) in direction (ex, ey) applied to the midpoint
-// deviations (d0, d1, d2), in FP32 with the hardware reciprocal and square
-// root.  Returns true only if |a1| <= thr holds for the FP64 evaluation of
-// the same inputs: the FP32 result is widened by a bound of its rounding
-// error (unit roundoff u = 2^-24; inputs, rcp and sqrt within 2u, the row
-// within 16u (c + |ub| + |vb|) i2c, each product and sum within 2u), taken
-// with a factor 2 to spare.
-__device__ __forceinline__ bool tvb_screen_small(double hb, double mu, double mv, float g, float ex,
-                                                 float ey, int r, double d0, double d1, double d2,
-                                                 float thr) {
-    const float h = (float)hb;
-    const float ih = __builtin_amdgcn_rcpf(h);
-    const float ub = (float)mu * ih, vb = (float)mv * ih;
-    const float c = __builtin_amdgcn_sqrtf(g * h);
-    const float i2c = 0.5f * __builtin_amdgcn_rcpf(c);
-    const float un = ub * ex + vb * ey, ut = vb * ex - ub * ey;
-    float L0, L1, L2;
-    if (r == 1) {
-        L0 = -ut;
-        L1 = -ey;
-        L2 = ex;
-    } else {
-        const float sg = r == 0 ? -1.f : 1.f;
-        L0 = (c - sg * un) * i2c;
-        L1 = sg * ex * i2c;
-        L2 = sg * ey * i2c;
-    }
-    const float t0 = L0 * (float)d0, t1 = L1 * (float)d1, t2 = L2 * (float)d2;
-    const float a1 = t0 + t1 + t2;
-    const float err = 0x1p-19f * ((c + fabsf(ub) + fabsf(vb)) * (i2c + 1.f) * fabsf((float)d0) +
-                                  fabsf(t0) + fabsf(t1) + fabsf(t2));
-    return fabsf(a1) + err <= thr;
-}
-
 // ---------------------------------------------------------------------------
 // step kernel with the contraction on the matrix cores (N <= 4, Np <= 16)
 //
@@ -547,9 +512,9 @@ struct MShape {
     static constexpr int Np = (N + 1) * (N + 2) / 2;
     static constexpr int Nfp = N + 1;
     static constexpr int nF = 3 * (N + 1);
-    static constexpr int KT = 2 * Np + nF;        // contraction length
-    static constexpr int KS = (KT + 3) / 4;       // MFMA steps of K = 4
-    static constexpr int KB = (2 * Np + 3) / 4;   // steps covering the Dr/Ds columns
+    static constexpr int KV = mfma_kv(N);         // first LIFT column (volume part padded)
+    static constexpr int KS = mfma_steps(N);      // MFMA steps of K = 4
+    static constexpr int SV = KV / 4;             // volume-only steps (Dr/Ds columns)
     static constexpr int KSP = (KS + 3) & ~3;     // steps padded to whole float4 reads
     static constexpr int RS = 4 * KSP + 4;        // LDS row stride (floats)
     static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
@@ -587,10 +552,11 @@ __device__ __forceinline__ void stg(T* base, unsigned i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
 }
 
-template <int N, bool MULTI>
-__global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
+template <int N, bool MULTI, int WPB>
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(MULTI ? 6 : 7, 8)))
+step_mfma_kernel(StepArgs a) {
     using S = MShape<N>;
-    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KT = S::KT, KS = S::KS, KB = S::KB;
+    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KV = S::KV, KS = S::KS, SV = S::SV;
     constexpr int KSP = S::KSP, RS = S::RS;
     // LDS is per wave (its four elements): the X^T rows, and after they have
     // been read into registers, the FP64 node values and reductions in the
@@ -604,7 +570,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             } r;
         };
     };
-    __shared__ __attribute__((aligned(16))) WaveLds lds[4];
+    __shared__ __attribute__((aligned(16))) WaveLds lds[WPB];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -614,7 +580,7 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     double (&sVd)[4][3][16] = lds[wave].r.Vd;
     double (&sRed)[4][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = a.k_begin + blk * 16 + el;
+    const int k = a.k_begin + blk * (4 * WPB) + el;
     const bool live = k < a.k_end;
     const bool node = live && j < Np;
     // loads are unconditional: lanes past the last element read the last
@@ -682,12 +648,6 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
             hvP = ldg(a.half + 2 * (size_t)KnF, hid);
         }
     }
-    float opB[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
-    double wred[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) wred[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
 
     const float eta0 = __shfl(eta, lane & ~15);
     const float lo0 = __shfl(lo, lane & ~15);
@@ -715,13 +675,43 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         sA[q][4][kperm<KSP>(Np + j)] = sy * bb;
     }
     if (j < nF) {   // lift columns of the bed rows are zero
-        sA[q][3][kperm<KSP>(2 * Np + j)] = 0.f;
-        sA[q][4][kperm<KSP>(2 * Np + j)] = 0.f;
+        sA[q][3][kperm<KSP>(KV + j)] = 0.f;
+        sA[q][4][kperm<KSP>(KV + j)] = 0.f;
     }
-    if (j < 4 * KSP - KT) {   // K padding of all rows
+    if (j < KV - 2 * Np) {   // padding after the volume columns (finite: the operator is 0 there)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(KT + j)] = 0.f;
+        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(2 * Np + j)] = 0.f;
     }
+    if (j < 4 * KSP - (KV + nF)) {   // padding after the lift columns
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(KV + nF + j)] = 0.f;
+    }
+    wave_lds_sync();
+
+    // ---- volume part of the contraction on the matrix cores, issued before
+    // the face flux so that it overlaps the neighbour loads
+    const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
+    const int ag = lane >> 4;           // K group supplied by this lane
+    constexpr int SV4 = (SV + 3) / 4;   // float4 chunks covering the volume steps
+    float av[4 * SV4], ay[4 * SV4];
+#pragma unroll
+    for (int s4 = 0; s4 < SV4; ++s4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][ar & 3][ag * KSP + 4 * s4]);
+        const float4 y4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][4][ag * KSP + 4 * s4]);
+        av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
+        ay[4 * s4] = y4.x; ay[4 * s4 + 1] = y4.y; ay[4 * s4 + 2] = y4.z; ay[4 * s4 + 3] = y4.w;
+    }
+    float opB[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < SV; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
+    floatx4 accy = {0.f, 0.f, 0.f, 0.f};
+    const bool rowy = (ar & 3) == 0;
+#pragma unroll
+    for (int s = 0; s < SV; ++s)
+        accy = __builtin_amdgcn_mfma_f32_16x16x4f32(rowy ? ay[s] : 0.f, opB[s], accy, 0, 0, 0);
 
     // ---- face node fn = j of element q: reconstructed states, LLF flux
     const float etaM = __shfl(eta, (lane & ~15) + n);
@@ -757,32 +747,24 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
         const float ah = hsM * unM + hsP * unP;
         const float au = hsM * uM * unM + hsP * uP * unP;
         const float av = hsM * vM * unM + hsP * vP * unP;
-        const int kp = kperm<KSP>(2 * Np + fn);
+        const int kp = kperm<KSP>(KV + fn);
         sA[q][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
         sA[q][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
         sA[q][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
     }
     wave_lds_sync();
 
-    // ---- contraction on the matrix cores
-    const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
-    const int ag = lane >> 4;           // K group supplied by this lane
-    float av[KSP], ay[KSP];
+    // ---- lift part of the contraction (steps SV .. KS-1)
+    constexpr int F0 = SV / 4, F1 = (KS + 3) / 4;   // float4 chunks holding the lift steps
+    float af[4 * (F1 - F0)];
 #pragma unroll
-    for (int s4 = 0; s4 < KSP / 4; ++s4) {
+    for (int s4 = F0; s4 < F1; ++s4) {
         const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][ar & 3][ag * KSP + 4 * s4]);
-        const float4 y4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][4][ag * KSP + 4 * s4]);
-        av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
-        ay[4 * s4] = y4.x; ay[4 * s4 + 1] = y4.y; ay[4 * s4 + 2] = y4.z; ay[4 * s4 + 3] = y4.w;
+        af[4 * (s4 - F0)] = v4.x; af[4 * (s4 - F0) + 1] = v4.y;
+        af[4 * (s4 - F0) + 2] = v4.z; af[4 * (s4 - F0) + 3] = v4.w;
     }
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
-    floatx4 accy = {0.f, 0.f, 0.f, 0.f};
-    const bool rowy = (ar & 3) == 0;
-#pragma unroll
-    for (int s = 0; s < KB; ++s)
-        accy = __builtin_amdgcn_mfma_f32_16x16x4f32(rowy ? ay[s] : 0.f, opB[s], accy, 0, 0, 0);
+    for (int s = SV; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s - 4 * F0], opB[s], acc, 0, 0, 0);
     float Rn[3];
     Rn[0] = acc[0];
     Rn[1] = acc[1] - g * dlt * acc[3];
@@ -827,6 +809,9 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, 16));
     wave_lds_sync();
+    double wred[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) wred[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
         const int c = lane & 15;          // column: element c/4, field c%4
@@ -864,26 +849,14 @@ __global__ void __launch_bounds__(256) step_mfma_kernel(StepArgs a) {
     const double mean0 = code == 2 ? hdry : hb;
     const double mean1 = code == 2 ? 0.0 : sRed[q][2];
     const double mean2 = code == 2 ? 0.0 : sRed[q][3];
-    // ---- TVB screen: lane j < 9 checks component j % 3 of edge j / 3 in FP32
-    // with a bound on its rounding error, so an element leaves the candidate
-    // set only when the FP64 test would keep every component too
-    bool small = true;
-    double devw = 0.0;
-    if (live && j < 9) {
-        const int ed = j / 3, r = j % 3;
-        devw = scale * sRed[q][4 + 3 * r + ed];   // deviation of field r at edge ed
-        if (a.tvb_on && code != 2) {
-            const float* st = a.stencil + 16u * k;
-            small = tvb_screen_small(mean0, mean1, mean2, g, st[4 * ed + 2], st[4 * ed + 3], r,
-                                     scale * sRed[q][4 + ed], scale * sRed[q][7 + ed],
-                                     scale * sRed[q][10 + ed], st[12]);
-        }
-    }
-    const unsigned long long bal = __ballot(small);
-    const bool candidate = a.tvb_on && code != 2 && ((bal >> (16 * q)) & 0x1FFull) != 0x1FFull;
+    // ---- hand-off to the TVB kernel: post-limiter means of every element,
+    // P1 midpoint deviations of every element that is not dry
     if (live && j < 3) stg(a.means, (unsigned)j * (unsigned)a.K + k, j == 0 ? mean0 : (j == 1 ? mean1 : mean2));
-    if (candidate && j < 9) stg(a.devs, (unsigned)(3 * (j % 3) + j / 3) * (unsigned)a.K + k, devw);
-    if (live && j == 0) a.flags[k] = (uint8_t)(code | (candidate ? kTvbCandidate : 0));
+    if (live && j < 9 && code != 2) {
+        const int ed = j / 3, r = j % 3;   // field r at edge ed
+        stg(a.devs, (unsigned)(3 * r + ed) * (unsigned)a.K + k, scale * sRed[q][4 + 3 * r + ed]);
+    }
+    if (live && j == 0) a.flags[k] = (uint8_t)(code | (code != 2 ? kTvbCandidate : 0));
     if (!node) return;
     // ---- limited nodal values and the new state
     float out[3] = {qn[0], qn[1], qn[2]};
@@ -1141,55 +1114,64 @@ static int check_launch(const char* what) {
 }
 
 int step_elems_per_block(int N, int engine) {
-    (void)engine;
-    const int Np = (N + 1) * (N + 2) / 2;
-    return 256 / Np;
+    if (engine == ENGINE_MFMA_F32 && N <= 4) return kMfmaDefaultElems;
+    return 256 / ((N + 1) * (N + 2) / 2);
 }
 
 // kernel launch; with a start/stop event pair the events take the kernel's
 // own start and end timestamps from its dispatch (no queue or launch gaps)
 template <typename K>
-static void dispatch(K kernel, int blocks, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
+static void dispatch(K kernel, int blocks, int threads, hipStream_t s, const StepArgs& a, hipEvent_t e0,
+                     hipEvent_t e1) {
     if (e0 != nullptr)
-        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), 0, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), 0, s, a);
+}
+
+// matrix-core step kernel with W waves (4 W elements) per block
+template <int N, int W>
+static void dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
+    const int blocks = (n + 4 * W - 1) / (4 * W);
+    if (a.nlev > 1)
+        dispatch(step_mfma_kernel<N, true, W>, blocks, 64 * W, s, a, e0, e1);
+    else
+        dispatch(step_mfma_kernel<N, false, W>, blocks, 64 * W, s, a, e0, e1);
 }
 
 template <int N>
-static int launch_step_n(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e0, hipEvent_t e1) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
     if constexpr (N <= 4) {
         if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_FUSED) {
-            if (a.nlev > 1)
-                dispatch(step_mfma_kernel<N, true>, (n + 15) / 16, s, a, e0, e1);
-            else
-                dispatch(step_mfma_kernel<N, false>, (n + 15) / 16, s, a, e0, e1);
+            switch (epb) {
+                case 4: dispatch_mfma<N, 1>(n, s, a, e0, e1); break;
+                case 8: dispatch_mfma<N, 2>(n, s, a, e0, e1); break;
+                case 16: dispatch_mfma<N, 4>(n, s, a, e0, e1); break;
+                default:
+                    std::snprintf(g_dev_err, sizeof(g_dev_err), "elements per block %d not in {4, 8, 16}", epb);
+                    return -1;
+            }
             return check_launch("step mfma kernel");
         }
     }
     const int E = Shape<N>::E;
-    dispatch(step_kernel<N>, (n + E - 1) / E, s, a, e0, e1);
+    dispatch(step_kernel<N>, (n + E - 1) / E, 256, s, a, e0, e1);
     return check_launch("step kernel");
 }
 
-int mfma_steps(int N) {
-    const int Np = (N + 1) * (N + 2) / 2, nF = 3 * (N + 1);
-    return (2 * Np + nF + 3) / 4;
-}
-
 int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_start, void* ev_stop) {
-    (void)elems_per_block;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = static_cast<hipEvent_t>(ev_start), e1 = static_cast<hipEvent_t>(ev_stop);
+    const int epb = elems_per_block > 0 ? elems_per_block : step_elems_per_block(a.N, a.engine);
     switch (a.N) {
-        case 1: return launch_step_n<1>(a, s, e0, e1);
-        case 2: return launch_step_n<2>(a, s, e0, e1);
-        case 3: return launch_step_n<3>(a, s, e0, e1);
-        case 4: return launch_step_n<4>(a, s, e0, e1);
-        case 5: return launch_step_n<5>(a, s, e0, e1);
-        case 6: return launch_step_n<6>(a, s, e0, e1);
+        case 1: return launch_step_n<1>(a, s, epb, e0, e1);
+        case 2: return launch_step_n<2>(a, s, epb, e0, e1);
+        case 3: return launch_step_n<3>(a, s, epb, e0, e1);
+        case 4: return launch_step_n<4>(a, s, epb, e0, e1);
+        case 5: return launch_step_n<5>(a, s, epb, e0, e1);
+        case 6: return launch_step_n<6>(a, s, epb, e0, e1);
         default:
             std::snprintf(g_dev_err, sizeof(g_dev_err), "unsupported N=%d", a.N);
             return -1;

@@ -8,8 +8,8 @@
 namespace dgswe {
 
 constexpr int kMaxLevels = 6;
-// flag bit set by the step kernels: the element needs the full TVB limiter
-// (not dry, and some characteristic midpoint increment exceeds M d^2)
+// flag bit set by the step kernels: the element goes through the TVB
+// limiter (it is not dry; its FP64 midpoint deviations were written)
 constexpr int kTvbCandidate = 16;
 
 // Face node fn = f (N+1) + p of the reference triangle (faces s = -1, r + s
@@ -84,9 +84,8 @@ struct StepArgs {
     uint8_t* flags;        // [K]
     unsigned long long* counters;  // [0] negative-mean events
     DevOps ops;
-    const float* stencil;  // [K][16] TVB stencil (in-kernel screen)
     float g, h0, eps, hvel;
-    int pp_on, dry_literal, tvb_on;
+    int pp_on, dry_literal;
 };
 
 struct TvbArgs {
@@ -129,8 +128,17 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
                 void* ev_stop = nullptr);
 int launch_tvb(const TvbArgs& a, void* stream);
 int launch_diag(const DiagArgs& a, void* stream);
+// elements per block: matrix-core kernel 4, 8 or 16 (1, 2 or 4 waves of four
+// elements); VALU kernel floor(256 / Np) (fixed)
+constexpr int kMfmaDefaultElems = 16;
 int step_elems_per_block(int N, int engine);
-int mfma_steps(int N);   // K = 4 steps of the MFMA contraction (N <= 4)
+
+// K layout of the matrix-core contraction (N <= 4): Dr columns 0..Np-1, Ds
+// columns Np..2Np-1, zero padding to mfma_kv(N) (a multiple of 4), LIFT
+// columns from mfma_kv(N); mfma_steps(N) steps of K = 4 in total, the first
+// mfma_kv(N) / 4 of them volume-only
+constexpr int mfma_kv(int N) { return ((N + 1) * (N + 2) + 3) & ~3; }
+constexpr int mfma_steps(int N) { return (mfma_kv(N) + 3 * (N + 1) + 3) / 4; }
 const char* device_error_string();
 
 }  // namespace dgswe

@@ -30,7 +30,8 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_destroy", "dg_last_error", "dg_
            "dg_reference_nodes", "dg_set_bathymetry", "dg_set_state", "dg_prepare",
            "dg_advance", "dg_get_state", "dg_get_connectivity", "dg_get_levels",
            "dg_get_tvb_stencil", "dg_get_flags", "dg_get_diagnostics", "dg_checkpoint_bytes",
-           "dg_get_checkpoint", "dg_set_checkpoint", "dg_set_profiling", "dg_kernel_timing"]
+           "dg_get_checkpoint", "dg_set_checkpoint", "dg_set_profiling", "dg_kernel_timing",
+           "dg_autotune"]
 
 
 class DGError(RuntimeError):
@@ -106,6 +107,7 @@ def load_library(path: Optional[str] = None):
         "dg_set_checkpoint": (_I32, [_P, _P, _I64, _P]),
         "dg_set_profiling": (_I32, [_P, _I32]),
         "dg_kernel_timing": (_I32, [_P, _D, C.POINTER(_I64), C.POINTER(_I64)]),
+        "dg_autotune": (_I32, [_P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _D, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -303,3 +305,13 @@ class Solver:
         e = _I64()
         _check(self.lib.dg_kernel_timing(self.h, C.byref(us), C.byref(n), C.byref(e)))
         return us.value, n.value, e.value
+
+    def autotune(self, reps: int = 10, stream=None):
+        """Time each elements-per-block candidate of the step kernel on the
+        current state and keep the fastest; returns [(elements, us), ...]."""
+        n = _I32()
+        epb = (_I32 * 8)()
+        us = (C.c_double * 8)()
+        _check(self.lib.dg_autotune(self.h, reps, 8, C.byref(n), epb,
+                                    C.cast(us, _D), C.c_void_p(self._stream(stream))))
+        return [(int(epb[i]), float(us[i])) for i in range(min(n.value, 8))]

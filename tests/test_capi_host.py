@@ -98,7 +98,18 @@ def test_error_paths():
     with pytest.raises(dgswe.DGError) as e:
         dgswe.Solver([(vx, vy, np.array([[0, 1, 2]]))], 2, tvb_nu=0.5)
     assert e.value.code == -1
+    tri = np.array([[0, 1, 2]])
+    for epb in (4, 8, 16):   # launch shapes of the matrix-core kernel
+        dgswe.Solver([(vx, vy, tri)], 3, precision="fused_mfma32", elems_per_block=epb)
+    for bad, prec in ((12, "fused_mfma32"), (16, "fused_fp32"), (-4, "fused_mfma32")):
+        with pytest.raises(dgswe.DGError) as e:
+            dgswe.Solver([(vx, vy, tri)], 3, precision=prec, elems_per_block=bad)
+        assert e.value.code == -1
+    dgswe.Solver([(vx, vy, tri)], 3, precision="fused_fp32", elems_per_block=25)   # 256 // Np
     s = dgswe.Solver([(vx, vy, np.array([[0, 1, 3], [0, 3, 2]]))], 2)
+    with pytest.raises(dgswe.DGError) as e:           # no state to tune on
+        s.autotune(stream=_NoStream())
+    assert e.value.code == -5
     x, _ = s.node_coords(0)
     s.set_bathymetry(0, np.zeros_like(x))
     with pytest.raises(dgswe.DGError) as e:           # nothing bound yet

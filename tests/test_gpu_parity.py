@@ -94,11 +94,22 @@ def test_wetdry_parity(path):
     assert d["pp_counts"][1] + d["pp_counts"][2] > 0
 
 
-def test_lake_at_rest_exact_on_gpu():
+@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("path", PATHS)
+def test_low_orders_wetdry(path, N):
+    """Orders 1 and 2 (every instantiation of the step kernels) on the small
+    wet/dry beach, 60 steps against the oracle."""
+    g, o, q = _compare(f"wetdry-N{N}", W.small_wetdry(n=12, N=N), 60, precision=path, flip_frac=0.01)
+    assert g.diagnostics(0)["min_depth"] >= 0.0
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("path", PATHS)
+def test_lake_at_rest_exact_on_gpu(path, N):
     _require_gpu()
-    wl = W.lake_at_rest(n=8, N=4)
-    log("[lake-at-rest]")
-    g = gpu_solver(wl)
+    wl = W.lake_at_rest(n=8, N=N)
+    log(f"[lake-at-rest] {path} N={N}")
+    g = gpu_solver(wl, precision=path)
     g.prepare()
     h0, hu0, hv0 = g.get_state(0)
     g.advance(40)
@@ -107,12 +118,13 @@ def test_lake_at_rest_exact_on_gpu():
     assert np.all(hu1 == 0.0) and np.all(hv1 == 0.0)
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("path", PATHS)
+def test_graph_replay_matches_eager(path):
     _require_gpu()
     wl = W.small_wetdry(n=10, N=4)
-    log("[graph-vs-eager]")
-    a = gpu_solver(wl, use_graph=1)
-    b = gpu_solver(wl, use_graph=0)
+    log(f"[graph-vs-eager] {path}")
+    a = gpu_solver(wl, precision=path, use_graph=1)
+    b = gpu_solver(wl, precision=path, use_graph=0)
     for n in (7, 12, 5):
         a.advance(n)
         b.advance(n)
@@ -206,13 +218,44 @@ def test_bench_config_500_steps(path):
     assert pp_flips + tv_flips <= 0.002 * wl.n_elements
 
 
-def test_multirate_graded_bands():
+def test_block_shapes_and_autotune_bitwise():
+    """Elements per block (4, 8, 16) only changes the launch shape of the
+    matrix-core kernel: every element's arithmetic is wave-local, so the
+    trajectories agree bit for bit; the autotuner's trial launches leave the
+    state, flags and counters as the next step expects them."""
+    _require_gpu()
+    wl = W.small_wetdry(n=12, N=4)
+    log("[block-shapes]")
+    ref = gpu_solver(wl, precision="fused_mfma32", elems_per_block=16)
+    ref.advance(30)
+    want = ref.get_state(0)
+    for epb in (4, 8):
+        g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
+        g.advance(30)
+        for x, y in zip(g.get_state(0), want):
+            assert np.array_equal(x, y)
+    t = gpu_solver(wl, precision="fused_mfma32")
+    t.advance(7)
+    f0 = t.flags(0)
+    d0 = t.diagnostics(0)
+    res = t.autotune(reps=3)
+    log(f"[block-shapes] autotune {res}")
+    assert sorted(e for e, _ in res) == [4, 8, 16] and all(us > 0 for _, us in res)
+    assert np.array_equal(t.flags(0), f0)
+    assert t.diagnostics(0)["negative_means"] == d0["negative_means"]
+    t.advance(23)
+    for x, y in zip(t.get_state(0), want):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_multirate_graded_bands(path):
     """Multi-rate AB3 on a graded band mesh (4 levels) against the oracle's
     tick schedule (Section 4, Algorithm 4.1): 6 coarse steps = 48 ticks."""
     _require_gpu()
     wl = W.c3(n0=3)
-    log(f"[mrab] K={wl.n_elements} levels=4")
-    g = gpu_solver(wl)
+    log(f"[mrab] {path} K={wl.n_elements} levels=4")
+    g = gpu_solver(wl, precision=path)
     o = oracle_solver(wl)
     lev, dt = g.levels(0)
     assert np.array_equal(lev.astype(int), o.levels)
@@ -226,12 +269,13 @@ def test_multirate_graded_bands():
     assert pp + tv == 0
 
 
-def test_multirate_graph_matches_eager():
+@pytest.mark.parametrize("path", PATHS)
+def test_multirate_graph_matches_eager(path):
     _require_gpu()
     wl = W.c3(n0=2)
-    log("[mrab-graph]")
-    a = gpu_solver(wl, use_graph=1)
-    b = gpu_solver(wl, use_graph=0)
+    log(f"[mrab-graph] {path}")
+    a = gpu_solver(wl, precision=path, use_graph=1)
+    b = gpu_solver(wl, precision=path, use_graph=0)
     a.advance(9)
     b.advance(9)
     for x, y in zip(a.get_state(0), b.get_state(0)):
