@@ -55,7 +55,10 @@ extern "C" {
 #define DG_PLAIN_FP32     0  /* separate RHS, update and limiter kernels, FP32 VALU  */
 #define DG_FUSED_FP32     1  /* fused RHS+AB3+positivity kernel, FP32 VALU matvecs   */
 #define DG_FUSED_MFMA32   2  /* fused kernel, [Dr Ds LIFT] contraction on FP32 MFMA  */
-#define DG_FUSED_BF16X3   3  /* fused kernel, BF16 hi/lo split MFMA, FP32 accumulate */
+#define DG_FUSED_BF16X3   3  /* fused kernel, BF16 MFMA, operands split in 2 parts,  */
+                             /* 3 products, FP32 accumulate (N <= 4)               */
+#define DG_FUSED_BF16X6   4  /* fused kernel, BF16 MFMA, operands split in 3 parts,  */
+                             /* 6 products, FP32 accumulate (N <= 4)               */
 
 /* limiter switches (dg_params.limiter_mask) */
 #define DG_LIMIT_PP   1      /* positivity limiter, Algorithm 5.2         */

@@ -38,8 +38,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t Q[2], R[3], half, means, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
-    size_t B, geo, conn, stencil;
-    size_t Dr, Ds, LIFT, Amfma, Wred, fmask, nodeface, wh, pmid, phi, wfull;
+    size_t B, dB, geo, conn, stencil;
+    size_t Dr, Ds, LIFT, Amfma, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
     size_t diag_partial, diag_out;
     size_t total;
 };
@@ -70,7 +70,7 @@ struct dg_solver {
     bool bound = false, prepared = false;
     int device = 0;
     // host staging (sorted order, FP32)
-    std::vector<float> geo, stencil, Bh, Qh;   // Qh: [4][K*Np] (eta hi, hu, hv, eta lo); Bh, eta relative to the datum
+    std::vector<float> geo, stencil, Bh, Qh, dBh;   // dBh: [2][K*Np] bed gradient   // Qh: [4][K*Np] (eta hi, hu, hv, eta lo); Bh, eta relative to the datum
     std::vector<double> B64;                   // bed elevation, FP64, sorted order
     std::vector<int> conn;
     // time stepping state
@@ -94,10 +94,25 @@ static const float kAB[3][3] = {{1.f, 0.f, 0.f}, {1.5f, -0.5f, 0.f},
 static const float kHalf[3][3] = {{0.5f, 0.f, 0.f}, {5.f / 8.f, -1.f / 8.f, 0.f},
                                   {17.f / 24.f, -7.f / 24.f, 2.f / 24.f}};
 
+// bfloat16 of an FP32 value, round to nearest even (finite inputs), and back
+static uint16_t bf16_round(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+static float bf16_value(uint16_t b) {
+    const uint32_t u = uint32_t(b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
 static int engine_of(int precision) {
     switch (precision) {
         case DG_FUSED_MFMA32: return ENGINE_MFMA_F32;
         case DG_FUSED_BF16X3: return ENGINE_MFMA_BF16X3;
+        case DG_FUSED_BF16X6: return ENGINE_MFMA_BF16X6;
         default: return ENGINE_VALU;
     }
 }
@@ -122,6 +137,7 @@ static void compute_layout(dg_solver* h) {
     l.counters = take(64);
     l.dyn_end = o;
     l.B = take(KNp * 4);
+    l.dB = take(2 * KNp * 4);
     l.geo = take(size_t(h->K) * 64);
     l.conn = take(size_t(h->K) * 16);
     l.stencil = take(size_t(h->K) * 64);
@@ -130,6 +146,7 @@ static void compute_layout(dg_solver* h) {
     l.Ds = take(size_t(Np) * Np * 4);
     l.LIFT = take(size_t(Np) * nF * 4);
     l.Amfma = take(size_t(64) * 256 * 4 * 2);
+    l.Abf = take(size_t(8) * 64 * 48);
     l.Wred = take(size_t(4) * 64 * 8);
     l.fmask = take(size_t(nF) * 4);
     l.nodeface = take(size_t(Np) * 2 * 4);
@@ -177,14 +194,12 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         return fail(DG_EINVAL, "bad physical or limiter parameter");
     if (p->max_levels < 1 || p->max_levels > kMaxLevels)
         return fail(DG_EINVAL, "max_levels must be in 1..6");
-    if (p->precision < DG_PLAIN_FP32 || p->precision > DG_FUSED_BF16X3)
+    if (p->precision < DG_PLAIN_FP32 || p->precision > DG_FUSED_BF16X6)
         return fail(DG_EINVAL, "unknown precision/path");
-    if (p->precision == DG_FUSED_BF16X3)
-        return fail(DG_EINVAL, "the BF16 split contraction is not available in this build");
-    if (p->precision == DG_FUSED_MFMA32 && p->N > 4)
+    if (p->precision >= DG_FUSED_MFMA32 && p->N > 4)
         return fail(DG_EINVAL, "the MFMA contraction needs Np <= 16 (N <= 4)");
     if (p->elems_per_block != 0) {
-        const bool mfma = p->precision == DG_FUSED_MFMA32;
+        const bool mfma = p->precision >= DG_FUSED_MFMA32;
         const int valu_e = 256 / ((p->N + 1) * (p->N + 2) / 2);
         const bool ok = mfma ? (p->elems_per_block == 4 || p->elems_per_block == 8 || p->elems_per_block == 16)
                              : p->elems_per_block == valu_e;
@@ -434,6 +449,30 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     HIPCHECK(up(l.Ds, Ds.data(), Ds.size() * 4));
     HIPCHECK(up(l.LIFT, LIFT.data(), LIFT.size() * 4));
     if (!amfma.empty()) HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
+    // BF16 engines: the same operator with K steps of 32, split into hi, mid
+    // and lo BF16 parts (op = hi + mid + lo to 2^-24 relative)
+    if (h->p.N <= 4) {
+        const int KV = (2 * Np + 31) & ~31, KS = (KV + nF + 31) / 32;
+        std::vector<uint16_t> abf(size_t(KS) * 64 * 24, 0);
+        for (int st = 0; st < KS; ++st)
+            for (int ln = 0; ln < 64; ++ln)
+                for (int i = 0; i < 8; ++i) {
+                    const int node = ln % 16, kk = 32 * st + 8 * (ln / 16) + i;
+                    double v = 0.0;
+                    if (node < Np) {
+                        if (kk < Np) v = re.Dr(node, kk);
+                        else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
+                        else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
+                    }
+                    float r = float(v);
+                    for (int t = 0; t < 3; ++t) {
+                        const uint16_t b = bf16_round(r);
+                        abf[(size_t(st) * 64 + ln) * 24 + 8 * t + i] = b;
+                        r -= bf16_value(b);
+                    }
+                }
+        HIPCHECK(up(l.Abf, abf.data(), abf.size() * 2));
+    }
     // FP64 MFMA A-operand of the element reductions: step s, lane l holds
     // W[row l % 16][node 4 s + l / 16], rows 0: w/2, 1-3: P1 midpoint - mean
     std::vector<double> wred(4 * 64, 0.0);
@@ -471,12 +510,24 @@ int32_t dg_set_bathymetry(dg_solver* h, int32_t inst, const double* B) {
     Inst& I = h->inst[inst];
     if (h->B64.empty()) h->B64.assign(size_t(h->K) * Np, 0.0);
     if (h->Bh.empty()) h->Bh.assign(size_t(h->K) * Np, 0.f);
+    if (h->dBh.empty()) h->dBh.assign(2 * size_t(h->K) * Np, 0.f);
+    for (size_t t = 0; t < size_t(I.mesh.K) * Np; ++t)
+        if (!std::isfinite(B[t])) return fail(DG_ENUMERIC, "non-finite bathymetry");
+    const size_t KNp = size_t(h->K) * Np;
     for (int k = 0; k < I.mesh.K; ++k) {
         const int s = h->inv[I.offset + k];
-        for (int j = 0; j < Np; ++j) {
-            const double b = B[size_t(k) * Np + j];
-            if (!std::isfinite(b)) return fail(DG_ENUMERIC, "non-finite bathymetry");
-            h->B64[size_t(s) * Np + j] = b;
+        const double* b = B + size_t(k) * Np;
+        for (int j = 0; j < Np; ++j) h->B64[size_t(s) * Np + j] = b[j];
+        // gradient of the nodal bed polynomial: (rx Dr + sx Ds) B, (ry Dr + sy Ds) B
+        const HostMesh& m = I.mesh;
+        for (int i = 0; i < Np; ++i) {
+            double br = 0.0, bs = 0.0;
+            for (int j = 0; j < Np; ++j) {
+                br += h->re.Dr(i, j) * b[j];
+                bs += h->re.Ds(i, j) * b[j];
+            }
+            h->dBh[size_t(s) * Np + i] = float(m.rx[k] * br + m.sx[k] * bs);
+            h->dBh[KNp + size_t(s) * Np + i] = float(m.ry[k] * br + m.sy[k] * bs);
         }
     }
     I.has_state = false;
@@ -573,6 +624,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.nlev = h->L;
     for (int q = 0; q < 2; ++q) a.Q[q] = reinterpret_cast<float*>(h->ws + l.Q[q]);
     a.B = reinterpret_cast<const float*>(h->ws + l.B);
+    a.dB = reinterpret_cast<const float*>(h->ws + l.dB);
     for (int s = 0; s < 3; ++s) a.R[s] = reinterpret_cast<float*>(h->ws + l.R[s]);
     a.half = h->L > 1 ? reinterpret_cast<float*>(h->ws + l.half) : nullptr;
     a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
@@ -585,6 +637,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.ops.Ds = reinterpret_cast<const float*>(h->ws + l.Ds);
     a.ops.LIFT = reinterpret_cast<const float*>(h->ws + l.LIFT);
     a.ops.Amfma = reinterpret_cast<const float*>(h->ws + l.Amfma);
+    a.ops.Abf = h->ws + l.Abf;
     a.ops.fmask = reinterpret_cast<const int*>(h->ws + l.fmask);
     a.ops.nodeface = reinterpret_cast<const int*>(h->ws + l.nodeface);
     a.ops.wh = reinterpret_cast<const double*>(h->ws + l.wh);
@@ -736,6 +789,7 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
     for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
     HIPCHECK(hipMemcpyAsync(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->ws + l.dB, h->dBh.data(), h->dBh.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemsetAsync(h->ws + l.dyn_begin, 0, l.dyn_end - l.dyn_begin, s));
     for (int q = 0; q < kMaxLevels; ++q) {
         h->parity[q] = 0;
@@ -829,7 +883,7 @@ int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out,
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int> cand;
-    if (h->p.precision == DG_FUSED_MFMA32)
+    if (h->p.precision >= DG_FUSED_MFMA32)
         cand = {4, 8, 16};
     else
         cand = {step_elems_per_block(h->p.N, engine_of(h->p.precision))};

@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ float sDr[Np * Np], sDs[Np * Np], sL[Np * nF];
     __shared__ int sFm[nF];
     __shared__ float sQ[5][E * Np];       // eta (hi), hu, hv, B, eta (lo)
-    __shared__ float sX[7][E * Np];       // X_r (3 fields), X_s (3 fields), B - B_k
+    __shared__ float sX[6][E * Np];       // X_r (3 fields), X_s (3 fields)
     __shared__ float sT[5][E * nF];       // exterior eta (hi), hu, hv, B, eta (lo)
     __shared__ float sLam[E * nF];
     __shared__ float sF[3][E * nF];
@@ -174,9 +174,6 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         if (live) {
             const float h = (eta - Bn) + lo;
             dlt = (eta - sQ[0][e * Np]) + (lo - sQ[4][e * Np]);
-            // bed relative to the element's first node: the gradient of B is
-            // taken from O(H |grad B|) values instead of O(|B|) ones
-            sX[6][tid] = Bn - sQ[3][e * Np];
             const float fv = vel_factor(h, hvel);
             const float u = hu * fv;
             const float v = hv * fv;
@@ -294,7 +291,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         __syncthreads();
         // ---- R = -(Dr X_r + Ds X_s) + LIFT dF + source
         if (live) {
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, br = 0.f, bs = 0.f;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
             for (int j = 0; j < Np; ++j) {
                 const float dr = sDr[i * Np + j], ds = sDs[i * Np + j];
@@ -302,8 +299,6 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 a0 += dr * sX[0][b] + ds * sX[3][b];
                 a1 += dr * sX[1][b] + ds * sX[4][b];
                 a2 += dr * sX[2][b] + ds * sX[5][b];
-                br += dr * sX[6][b];
-                bs += ds * sX[6][b];
             }
             float l0 = 0.f, l1 = 0.f, l2 = 0.f;
 #pragma unroll
@@ -314,10 +309,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 l1 += lm * sF[1][b];
                 l2 += lm * sF[2][b];
             }
-            const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
             Rn[0] = l0 - a0;
-            Rn[1] = l1 - a1 - g * dlt * (rx * br + sx * bs);
-            Rn[2] = l2 - a2 - g * dlt * (ry * br + sy * bs);
+            Rn[1] = l1 - a1 - g * dlt * a.dB[idx];
+            Rn[2] = l2 - a2 - g * dlt * a.dB[KNp + idx];
         }
     }
     if (mode == MODE_RHS_ONLY) {
@@ -494,31 +488,80 @@ __device__ __forceinline__ void char_left(double hb, double mu, double mv, doubl
 // Lanes are element-aligned: a wave holds 4 elements, lane 16q + j is node j
 // of element q, and every LDS row a wave touches is its own, so waves only
 // order their own LDS traffic (no block barriers).
-// Contraction: R^T = X^T [Dr Ds LIFT]^T on v_mfma_f32_16x16x4f32 with rows
+// Contraction: R^T = X^T [Dr Ds LIFT]^T on the matrix cores with rows
 // (element q, field f) and columns = nodes, so lane 16q + j receives R of
-// element q at node j for f = 0..3.  X^T rows: 0..2 = (-X_r, -X_s, dF) of h,
-// hu, hv; 3 = (rx (B - B_k), sx (B - B_k), 0) giving dB/dx; a second pass over
-// the Dr/Ds columns with row 4 = (ry (B - B_k), sy (B - B_k)) gives dB/dy.
-// Element reductions (means and P1 edge-midpoint deviations of h, hu, hv) are
-// W V on v_mfma_f64_16x16x4f64 in FP64 (W rows: w/2 and the three midpoint
-// functionals).  A TVB screen in FP64 marks the elements whose characteristic
-// midpoint increments all stay within M d^2 (kept without neighbour data).
+// element q at node j for f = 0..2.  X^T rows = (-X_r, -X_s, Fscale dF) of h,
+// hu, hv (row 3 of each element is not contracted).  Engines: FP32 on
+// v_mfma_f32_16x16x4f32, or BF16 on v_mfma_f32_16x16x32_bf16 with both
+// operands split into two or three BF16 parts and the split products
+// accumulated in FP32.  The bed gradient of the source term is static and
+// comes from the host (FP64).  Element reductions (means and P1
+// edge-midpoint deviations of h, hu, hv) are W V on v_mfma_f64_16x16x4f64 in
+// FP64 (W rows: w/2 and the three midpoint functionals).
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <int N>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// K layout of the X^T rows in LDS.  FP32 engine (v_mfma_f32_16x16x4f32): K
+// index k is supplied by lane group k % 4 at step k / 4.  BF16 engine
+// (v_mfma_f32_16x16x32_bf16): lane group g supplies K = 32 s + 8 g .. +7 at
+// step s.  Each group's values are contiguous so a lane reads its slice of a
+// row with float4 loads.
+template <int N, int BF>
 struct MShape {
     static constexpr int Np = (N + 1) * (N + 2) / 2;
     static constexpr int Nfp = N + 1;
     static constexpr int nF = 3 * (N + 1);
-    static constexpr int KV = mfma_kv(N);         // first LIFT column (volume part padded)
-    static constexpr int KS = mfma_steps(N);      // MFMA steps of K = 4
-    static constexpr int SV = KV / 4;             // volume-only steps (Dr/Ds columns)
-    static constexpr int KSP = (KS + 3) & ~3;     // steps padded to whole float4 reads
-    static constexpr int RS = 4 * KSP + 4;        // LDS row stride (floats)
+    static constexpr int KQ = BF ? 32 : 4;                            // K per MFMA step
+    static constexpr int KV = BF ? (2 * Np + 31) & ~31 : mfma_kv(N);  // first LIFT column
+    static constexpr int KS = BF ? (KV + nF + 31) / 32 : mfma_steps(N);
+    static constexpr int SV = KV / KQ;                                // volume-only steps
+    static constexpr int KSP = BF ? KS : (KS + 3) & ~3;               // FP32: steps padded to float4
+    static constexpr int RL = BF ? 32 * KS : 4 * KSP;                 // row length (floats)
+    static constexpr int RS = RL + 4;                                 // LDS row stride (floats)
     static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
+    static __device__ __forceinline__ int perm(int k) {
+        if constexpr (BF) return ((k >> 3) & 3) * (8 * KS) + (k >> 5) * 8 + (k & 7);
+        else return (k & 3) * KSP + (k >> 2);
+    }
 };
+
+// BF16 split of eight FP32 values into P parts: x_0 = bf16(x), x_1 =
+// bf16(x - x_0), x_2 = bf16(x - x_0 - x_1) (each remainder is exact in FP32)
+template <int P>
+__device__ __forceinline__ void bf16_split(const float4& x0, const float4& x1, bf16x8 (&part)[P]) {
+    const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float r = v[i];
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const __bf16 b = (__bf16)r;
+            part[t][i] = b;
+            if (t + 1 < P) r -= (float)b;
+        }
+    }
+}
+
+// split-precision products of one K = 32 step, accumulated in FP32 from the
+// smallest term up: P = 2: x1 o0 + x0 o1 + x0 o0; P = 3: x2 o0 + x1 o1 +
+// x0 o2 + x1 o0 + x0 o1 + x0 o0 (terms below 2^-24 of the product dropped)
+template <int P>
+__device__ __forceinline__ floatx4 bf16_products(const bf16x8 (&x)[P], const bf16x8* o, floatx4 acc) {
+    if constexpr (P == 2) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], o[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], o[1], acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], o[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], o[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], o[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], o[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], o[1], acc, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], o[0], acc, 0, 0, 0);
+}
 
 // face node fn of the reference element from a 4-bit packed table (N <= 4)
 template <int N>
@@ -526,13 +569,6 @@ __device__ __forceinline__ int face_node(int fn) {
     static_assert(N <= 4, "3(N+1) face nodes of 4 bits must fit 64 bits");
     constexpr unsigned long long bits = face_node_bits(N);
     return (int)((bits >> (4 * fn)) & 15ull);
-}
-
-template <int KSP>
-__device__ __forceinline__ int kperm(int k) {
-    // K index k is supplied by lane group k % 4 at step k / 4; each group's
-    // values are contiguous so a lane reads its row slice with float4 loads
-    return (k & 3) * KSP + (k >> 2);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -552,18 +588,18 @@ __device__ __forceinline__ void stg(T* base, unsigned i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
 }
 
-template <int N, bool MULTI, int WPB>
-__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(MULTI ? 6 : 7, 8)))
+template <int N, bool MULTI, int WPB, int BF>
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(BF == 2 ? (MULTI ? 4 : 5) : (BF ? (MULTI ? 5 : 6) : (MULTI ? 6 : 7)), 8)))
 step_mfma_kernel(StepArgs a) {
-    using S = MShape<N>;
+    using S = MShape<N, BF>;
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KV = S::KV, KS = S::KS, SV = S::SV;
-    constexpr int KSP = S::KSP, RS = S::RS;
+    constexpr int KSP = S::KSP, RS = S::RS, RL = S::RL;
     // LDS is per wave (its four elements): the X^T rows, and after they have
     // been read into registers, the FP64 node values and reductions in the
     // same bytes
     struct WaveLds {
         union {
-            float A[4][5][RS];
+            float A[4][3][RS];
             struct {
                 double Vd[4][3][16];   // updated h, hu, hv per node
                 double Red[4][16];     // 1-3 means, 4-12 deviations
@@ -576,7 +612,7 @@ step_mfma_kernel(StepArgs a) {
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, j = lane & 15;
     const int el = wave * 4 + q;
-    float (&sA)[4][5][RS] = lds[wave].A;
+    float (&sA)[4][3][RS] = lds[wave].A;
     double (&sVd)[4][3][16] = lds[wave].r.Vd;
     double (&sRed)[4][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -603,6 +639,7 @@ step_mfma_kernel(StepArgs a) {
     const float hv = ldg(Qi + 2 * (size_t)KNp, idx);
     const float lo = ldg(Qi + 3 * (size_t)KNp, idx);
     const float Bn = ldg(a.B, idx);
+    const float dBx = ldg(a.dB, idx), dBy = ldg(a.dB + KNp, idx);   // static bed gradient
     float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
     if (L.ab[1] != 0.f) {
         const float* R1 = a.R[L.slot[1]];
@@ -651,10 +688,9 @@ step_mfma_kernel(StepArgs a) {
 
     const float eta0 = __shfl(eta, lane & ~15);
     const float lo0 = __shfl(lo, lane & ~15);
-    const float B0 = __shfl(Bn, lane & ~15);
     const float dlt = (eta - eta0) + (lo - lo0);
 
-    // ---- X^T rows: volume fluxes (negated), bed-gradient rows, zero padding
+    // ---- X^T rows: volume fluxes (negated), zero padding
     if (node) {
         const float h = (eta - Bn) + lo;
         const float fv = 2.f * h * __builtin_amdgcn_rcpf(h * h + fmaxf(h * h, hvel * hvel));
@@ -665,53 +701,58 @@ step_mfma_kernel(StepArgs a) {
         const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sA[q][c][kperm<KSP>(j)] = -(rx * F[c] + ry * G[c]);
-            sA[q][c][kperm<KSP>(Np + j)] = -(sx * F[c] + sy * G[c]);
+            sA[q][c][S::perm(j)] = -(rx * F[c] + ry * G[c]);
+            sA[q][c][S::perm(Np + j)] = -(sx * F[c] + sy * G[c]);
         }
-        const float bb = Bn - B0;
-        sA[q][3][kperm<KSP>(j)] = rx * bb;
-        sA[q][3][kperm<KSP>(Np + j)] = sx * bb;
-        sA[q][4][kperm<KSP>(j)] = ry * bb;
-        sA[q][4][kperm<KSP>(Np + j)] = sy * bb;
     }
-    if (j < nF) {   // lift columns of the bed rows are zero
-        sA[q][3][kperm<KSP>(KV + j)] = 0.f;
-        sA[q][4][kperm<KSP>(KV + j)] = 0.f;
-    }
-    if (j < KV - 2 * Np) {   // padding after the volume columns (finite: the operator is 0 there)
+    // padding after the volume and after the lift columns (finite: the
+    // operator is zero there)
+    for (int t = j; t < KV - 2 * Np; t += 16) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(2 * Np + j)] = 0.f;
+        for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + t)] = 0.f;
     }
-    if (j < 4 * KSP - (KV + nF)) {   // padding after the lift columns
+    for (int t = j; t < RL - (KV + nF); t += 16) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sA[q][c][kperm<KSP>(KV + nF + j)] = 0.f;
+        for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + t)] = 0.f;
     }
     wave_lds_sync();
 
     // ---- volume part of the contraction on the matrix cores, issued before
     // the face flux so that it overlaps the neighbour loads
-    const int ar = lane & 15;           // A-operand row: (element ar/4, field ar%4) of this wave
+    // A-operand row (element ar/4, field ar%4) of this wave; field row 3 is
+    // not contracted (its lanes read field 0 and their results are unused)
+    const int ar = lane & 15;
+    const int arow = (ar & 3) == 3 ? 0 : (ar & 3);
     const int ag = lane >> 4;           // K group supplied by this lane
-    constexpr int SV4 = (SV + 3) / 4;   // float4 chunks covering the volume steps
-    float av[4 * SV4], ay[4 * SV4];
-#pragma unroll
-    for (int s4 = 0; s4 < SV4; ++s4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][ar & 3][ag * KSP + 4 * s4]);
-        const float4 y4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][4][ag * KSP + 4 * s4]);
-        av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
-        ay[4 * s4] = y4.x; ay[4 * s4 + 1] = y4.y; ay[4 * s4 + 2] = y4.z; ay[4 * s4 + 3] = y4.w;
-    }
-    float opB[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (!BF) {
+        constexpr int SV4 = (SV + 3) / 4;   // float4 chunks covering the volume steps
+        float av[4 * SV4];
 #pragma unroll
-    for (int s = 0; s < SV; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
-    floatx4 accy = {0.f, 0.f, 0.f, 0.f};
-    const bool rowy = (ar & 3) == 0;
+        for (int s4 = 0; s4 < SV4; ++s4) {
+            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][arow][ag * KSP + 4 * s4]);
+            av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
+        }
+        float opB[SV];
 #pragma unroll
-    for (int s = 0; s < SV; ++s)
-        accy = __builtin_amdgcn_mfma_f32_16x16x4f32(rowy ? ay[s] : 0.f, opB[s], accy, 0, 0, 0);
+        for (int s = 0; s < SV; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
+#pragma unroll
+        for (int s = 0; s < SV; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
+    } else {
+        // X and the operator split into P = BF + 1 BF16 parts; the operator
+        // table holds hi, mid, lo parts (the two-part split uses hi, mid)
+        constexpr int P = BF + 1;
+        const bf16x8* tab = reinterpret_cast<const bf16x8*>(a.ops.Abf);
+#pragma unroll
+        for (int s = 0; s < SV; ++s) {
+            const float* xp = &sA[ar >> 2][arow][ag * 8 * KS + 8 * s];
+            bf16x8 xs[P], o[P];
+            bf16_split<P>(*reinterpret_cast<const float4*>(xp), *reinterpret_cast<const float4*>(xp + 4), xs);
+#pragma unroll
+            for (int t = 0; t < P; ++t) o[t] = ldg(tab, (unsigned)(3 * (s * 64 + lane) + t));
+            acc = bf16_products<P>(xs, o, acc);
+        }
+    }
 
     // ---- face node fn = j of element q: reconstructed states, LLF flux
     const float etaM = __shfl(eta, (lane & ~15) + n);
@@ -747,7 +788,7 @@ step_mfma_kernel(StepArgs a) {
         const float ah = hsM * unM + hsP * unP;
         const float au = hsM * uM * unM + hsP * uP * unP;
         const float av = hsM * vM * unM + hsP * vP * unP;
-        const int kp = kperm<KSP>(KV + fn);
+        const int kp = S::perm(KV + fn);
         sA[q][0][kp] = fs * ((huM * nx + hvM * ny) - 0.5f * ah - 0.5f * lam * dh);
         sA[q][1][kp] = fs * (huM * unM - 0.5f * au + dp * nx + 0.5f * lam * (hsP * uP - hsM * uM));
         sA[q][2][kp] = fs * (hvM * unM - 0.5f * av + dp * ny + 0.5f * lam * (hsP * vP - hsM * vM));
@@ -755,20 +796,36 @@ step_mfma_kernel(StepArgs a) {
     wave_lds_sync();
 
     // ---- lift part of the contraction (steps SV .. KS-1)
-    constexpr int F0 = SV / 4, F1 = (KS + 3) / 4;   // float4 chunks holding the lift steps
-    float af[4 * (F1 - F0)];
+    if constexpr (!BF) {
+        constexpr int F0 = SV / 4, F1 = (KS + 3) / 4;   // float4 chunks holding the lift steps
+        float af[4 * (F1 - F0)];
 #pragma unroll
-    for (int s4 = F0; s4 < F1; ++s4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][ar & 3][ag * KSP + 4 * s4]);
-        af[4 * (s4 - F0)] = v4.x; af[4 * (s4 - F0) + 1] = v4.y;
-        af[4 * (s4 - F0) + 2] = v4.z; af[4 * (s4 - F0) + 3] = v4.w;
+        for (int s4 = F0; s4 < F1; ++s4) {
+            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][arow][ag * KSP + 4 * s4]);
+            af[4 * (s4 - F0)] = v4.x; af[4 * (s4 - F0) + 1] = v4.y;
+            af[4 * (s4 - F0) + 2] = v4.z; af[4 * (s4 - F0) + 3] = v4.w;
+        }
+#pragma unroll
+        for (int s = SV; s < KS; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s - 4 * F0], ldg(a.ops.Amfma, (unsigned)(s * 64 + lane)),
+                                                       acc, 0, 0, 0);
+    } else {
+        constexpr int P = BF + 1;
+        const bf16x8* tab = reinterpret_cast<const bf16x8*>(a.ops.Abf);
+#pragma unroll
+        for (int s = SV; s < KS; ++s) {
+            const float* xp = &sA[ar >> 2][arow][ag * 8 * KS + 8 * s];
+            bf16x8 xs[P], o[P];
+            bf16_split<P>(*reinterpret_cast<const float4*>(xp), *reinterpret_cast<const float4*>(xp + 4), xs);
+#pragma unroll
+            for (int t = 0; t < P; ++t) o[t] = ldg(tab, (unsigned)(3 * (s * 64 + lane) + t));
+            acc = bf16_products<P>(xs, o, acc);
+        }
     }
-#pragma unroll
-    for (int s = SV; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s - 4 * F0], opB[s], acc, 0, 0, 0);
     float Rn[3];
     Rn[0] = acc[0];
-    Rn[1] = acc[1] - g * dlt * acc[3];
-    Rn[2] = acc[2] - g * dlt * accy[0];
+    Rn[1] = acc[1] - g * dlt * dBx;
+    Rn[2] = acc[2] - g * dlt * dBy;
 
     // ---- Adams-Bashforth update, RHS ring, half-step traces
     float qn[3] = {eta, hu, hv};
@@ -1114,7 +1171,7 @@ static int check_launch(const char* what) {
 }
 
 int step_elems_per_block(int N, int engine) {
-    if (engine == ENGINE_MFMA_F32 && N <= 4) return kMfmaDefaultElems;
+    if (engine != ENGINE_VALU && N <= 4) return kMfmaDefaultElems;
     return 256 / ((N + 1) * (N + 2) / 2);
 }
 
@@ -1133,10 +1190,16 @@ static void dispatch(K kernel, int blocks, int threads, hipStream_t s, const Ste
 template <int N, int W>
 static void dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
     const int blocks = (n + 4 * W - 1) / (4 * W);
-    if (a.nlev > 1)
-        dispatch(step_mfma_kernel<N, true, W>, blocks, 64 * W, s, a, e0, e1);
-    else
-        dispatch(step_mfma_kernel<N, false, W>, blocks, 64 * W, s, a, e0, e1);
+    const int bf = a.engine == ENGINE_MFMA_BF16X3 ? 1 : (a.engine == ENGINE_MFMA_BF16X6 ? 2 : 0);
+    if (a.nlev > 1) {
+        if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, a, e0, e1);
+        else if (bf == 2) dispatch(step_mfma_kernel<N, true, W, 2>, blocks, 64 * W, s, a, e0, e1);
+        else dispatch(step_mfma_kernel<N, true, W, 0>, blocks, 64 * W, s, a, e0, e1);
+    } else {
+        if (bf == 1) dispatch(step_mfma_kernel<N, false, W, 1>, blocks, 64 * W, s, a, e0, e1);
+        else if (bf == 2) dispatch(step_mfma_kernel<N, false, W, 2>, blocks, 64 * W, s, a, e0, e1);
+        else dispatch(step_mfma_kernel<N, false, W, 0>, blocks, 64 * W, s, a, e0, e1);
+    }
 }
 
 template <int N>
@@ -1144,7 +1207,7 @@ static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
     if constexpr (N <= 4) {
-        if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_FUSED) {
+        if (a.engine != ENGINE_VALU && a.mode == MODE_FUSED) {
             switch (epb) {
                 case 4: dispatch_mfma<N, 1>(n, s, a, e0, e1); break;
                 case 8: dispatch_mfma<N, 2>(n, s, a, e0, e1); break;

@@ -39,7 +39,7 @@ enum StepMode : int {
 };
 
 // Contraction engine of the step kernel.
-enum Engine : int { ENGINE_VALU = 0, ENGINE_MFMA_F32 = 1, ENGINE_MFMA_BF16X3 = 2 };
+enum Engine : int { ENGINE_VALU = 0, ENGINE_MFMA_F32 = 1, ENGINE_MFMA_BF16X3 = 2, ENGINE_MFMA_BF16X6 = 3 };
 
 struct LevelArgs {
     int begin, end;        // element range of the level (sorted order)
@@ -56,7 +56,9 @@ struct DevOps {
     const float* Dr;       // Np x Np
     const float* Ds;       // Np x Np
     const float* LIFT;     // Np x 3Nfp
-    const float* Amfma;    // MFMA operator tiles (engine dependent) or null
+    const float* Amfma;    // FP32 MFMA B operand: step s, lane l -> Op[l % 16][4 s + l / 16]
+    const void* Abf;       // BF16 MFMA B operand: step s, lane l -> hi, mid, lo parts (8 bf16
+                           // each) of Op[l % 16][32 s + 8 (l / 16) + i], i = 0..7
     const int* fmask;      // 3Nfp
     const int* nodeface;   // Np x 2 (face-node slot of each volume node, -1 none)
     const double* wh;      // Np: w / 2 (cell-mean weights)
@@ -75,6 +77,7 @@ struct StepArgs {
     LevelArgs lev[kMaxLevels];
     float* Q[2];           // ping-pong state buffers [4][K*Np]: eta (hi), hu, hv, eta (lo)
     const float* B;        // [K*Np]
+    const float* dB;       // [2][K*Np] dB/dx, dB/dy at the nodes (static, from FP64 on the host)
     float* R[3];           // ring slots [3][K*Np]
     float* half;           // [3][K*3Nfp] half-step face traces (multi-rate) or null
     const float* geo;      // [K][16]

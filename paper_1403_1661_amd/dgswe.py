@@ -19,9 +19,10 @@ DG_OK = 0
 ERRORS = {-1: "DG_EINVAL", -2: "DG_EMESH", -3: "DG_ENOMEM", -4: "DG_EDEVICE",
           -5: "DG_ENOTBOUND", -6: "DG_ENUMERIC", -7: "DG_ESTATE"}
 
-DG_PLAIN_FP32, DG_FUSED_FP32, DG_FUSED_MFMA32, DG_FUSED_BF16X3 = 0, 1, 2, 3
+DG_PLAIN_FP32, DG_FUSED_FP32, DG_FUSED_MFMA32, DG_FUSED_BF16X3, DG_FUSED_BF16X6 = 0, 1, 2, 3, 4
 PRECISIONS = {"plain_fp32": DG_PLAIN_FP32, "fused_fp32": DG_FUSED_FP32,
-              "fused_mfma32": DG_FUSED_MFMA32, "fused_bf16x3": DG_FUSED_BF16X3}
+              "fused_mfma32": DG_FUSED_MFMA32, "fused_bf16x3": DG_FUSED_BF16X3,
+              "fused_bf16x6": DG_FUSED_BF16X6}
 DG_LIMIT_PP, DG_LIMIT_TVB = 1, 2
 
 # every symbol include/dgswe.h declares

@@ -106,6 +106,11 @@ def test_error_paths():
             dgswe.Solver([(vx, vy, tri)], 3, precision=prec, elems_per_block=bad)
         assert e.value.code == -1
     dgswe.Solver([(vx, vy, tri)], 3, precision="fused_fp32", elems_per_block=25)   # 256 // Np
+    for prec in ("fused_bf16x3", "fused_bf16x6"):     # BF16 split contraction: N <= 4
+        dgswe.Solver([(vx, vy, tri)], 4, precision=prec)
+        with pytest.raises(dgswe.DGError) as e:
+            dgswe.Solver([(vx, vy, tri)], 5, precision=prec)
+        assert e.value.code == -1
     s = dgswe.Solver([(vx, vy, np.array([[0, 1, 3], [0, 3, 2]]))], 2)
     with pytest.raises(dgswe.DGError) as e:           # no state to tune on
         s.autotune(stream=_NoStream())
