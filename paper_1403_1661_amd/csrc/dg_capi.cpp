@@ -147,7 +147,7 @@ static void compute_layout(dg_solver* h) {
     l.LIFT = take(size_t(Np) * nF * 4);
     l.Amfma = take(size_t(64) * 256 * 4 * 2);
     l.Abf = take(size_t(8) * 64 * 48);
-    l.Wred = take(size_t(4) * 64 * 8);
+    l.Wred = take(size_t(8) * 64 * 8);
     l.fmask = take(size_t(nF) * 4);
     l.nodeface = take(size_t(Np) * 2 * 4);
     l.wh = take(size_t(Np) * 8);
@@ -196,15 +196,17 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         return fail(DG_EINVAL, "max_levels must be in 1..6");
     if (p->precision < DG_PLAIN_FP32 || p->precision > DG_FUSED_BF16X6)
         return fail(DG_EINVAL, "unknown precision/path");
-    if (p->precision >= DG_FUSED_MFMA32 && p->N > 4)
-        return fail(DG_EINVAL, "the MFMA contraction needs Np <= 16 (N <= 4)");
+    if (p->precision >= DG_FUSED_MFMA32 && p->N > 5)
+        return fail(DG_EINVAL, "the MFMA contraction supports N <= 5");
     if (p->elems_per_block != 0) {
         const bool mfma = p->precision >= DG_FUSED_MFMA32;
         const int valu_e = 256 / ((p->N + 1) * (p->N + 2) / 2);
-        const bool ok = mfma ? (p->elems_per_block == 4 || p->elems_per_block == 8 || p->elems_per_block == 16)
-                             : p->elems_per_block == valu_e;
+        const int epw = 64 / mfma_lanes(p->N);
+        const int e = p->elems_per_block;
+        const bool ok = mfma ? (e == epw || e == 2 * epw || e == 4 * epw) : e == valu_e;
         if (!ok)
-            return fail(DG_EINVAL, mfma ? "elems_per_block must be 0, 4, 8 or 16 on the MFMA path"
+            return fail(DG_EINVAL, mfma ? "elems_per_block must be 0 or 1, 2, 4 waves of 64/lanes elements on "
+                                          "the MFMA paths (N <= 4: 4, 8, 16; N = 5: 2, 4, 8)"
                                         : "elems_per_block must be 0 or floor(256 / Np) on the VALU paths");
     }
     std::unique_ptr<dg_solver> h;
@@ -427,20 +429,24 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
         }
     // MFMA B-operand of [Dr Ds LIFT]^T in lane order: step s, lane l holds
     // Op[node l % 16][K index 4 s + l / 16] (0 outside Np x (2Np + 3Nfp))
+    // FP32 MFMA B operand: column tile t (nodes 16 t .. 16 t + 15), step st,
+    // lane ln -> Op[16 t + ln % 16][4 st + ln / 16]
     std::vector<float> amfma;
-    if (h->p.N <= 4) {
+    const int NT = mfma_lanes(h->p.N) / 16;
+    if (h->p.N <= 5) {
         const int KV = mfma_kv(h->p.N), KS = mfma_steps(h->p.N);
-        amfma.assign(size_t(KS) * 64, 0.f);
-        for (int st = 0; st < KS; ++st)
-            for (int ln = 0; ln < 64; ++ln) {
-                const int node = ln % 16, kk = 4 * st + ln / 16;
-                if (node >= Np) continue;
-                double v = 0.0;
-                if (kk < Np) v = re.Dr(node, kk);
-                else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
-                else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
-                amfma[size_t(st) * 64 + ln] = float(v);
-            }
+        amfma.assign(size_t(NT) * KS * 64, 0.f);
+        for (int t = 0; t < NT; ++t)
+            for (int st = 0; st < KS; ++st)
+                for (int ln = 0; ln < 64; ++ln) {
+                    const int node = 16 * t + ln % 16, kk = 4 * st + ln / 16;
+                    if (node >= Np) continue;
+                    double v = 0.0;
+                    if (kk < Np) v = re.Dr(node, kk);
+                    else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
+                    else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
+                    amfma[(size_t(t) * KS + st) * 64 + ln] = float(v);
+                }
     }
     auto up = [&](size_t off, const void* src, size_t n) {
         return hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, s);
@@ -451,33 +457,37 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     if (!amfma.empty()) HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
     // BF16 engines: the same operator with K steps of 32, split into hi, mid
     // and lo BF16 parts (op = hi + mid + lo to 2^-24 relative)
-    if (h->p.N <= 4) {
-        const int KV = (2 * Np + 31) & ~31, KS = (KV + nF + 31) / 32;
-        std::vector<uint16_t> abf(size_t(KS) * 64 * 24, 0);
-        for (int st = 0; st < KS; ++st)
-            for (int ln = 0; ln < 64; ++ln)
-                for (int i = 0; i < 8; ++i) {
-                    const int node = ln % 16, kk = 32 * st + 8 * (ln / 16) + i;
-                    double v = 0.0;
-                    if (node < Np) {
-                        if (kk < Np) v = re.Dr(node, kk);
-                        else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
-                        else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
+    if (h->p.N <= 5) {
+        const int KV = mfma_kv(h->p.N), KS = (KV + nF + 31) / 32;
+        std::vector<uint16_t> abf(size_t(NT) * KS * 64 * 24, 0);
+        for (int t = 0; t < NT; ++t)
+            for (int st = 0; st < KS; ++st)
+                for (int ln = 0; ln < 64; ++ln)
+                    for (int i = 0; i < 8; ++i) {
+                        const int node = 16 * t + ln % 16, kk = 32 * st + 8 * (ln / 16) + i;
+                        double v = 0.0;
+                        if (node < Np) {
+                            if (kk < Np) v = re.Dr(node, kk);
+                            else if (kk < 2 * Np) v = re.Ds(node, kk - Np);
+                            else if (kk >= KV && kk < KV + nF) v = re.LIFT(node, kk - KV);
+                        }
+                        float r = float(v);
+                        for (int u = 0; u < 3; ++u) {
+                            const uint16_t b = bf16_round(r);
+                            abf[((size_t(t) * KS + st) * 64 + ln) * 24 + 8 * u + i] = b;
+                            r -= bf16_value(b);
+                        }
                     }
-                    float r = float(v);
-                    for (int t = 0; t < 3; ++t) {
-                        const uint16_t b = bf16_round(r);
-                        abf[(size_t(st) * 64 + ln) * 24 + 8 * t + i] = b;
-                        r -= bf16_value(b);
-                    }
-                }
         HIPCHECK(up(l.Abf, abf.data(), abf.size() * 2));
     }
     // FP64 MFMA A-operand of the element reductions: step s, lane l holds
     // W[row l % 16][node 4 s + l / 16], rows 0: w/2, 1-3: P1 midpoint - mean
-    std::vector<double> wred(4 * 64, 0.0);
-    if (Np <= 16)
-        for (int st = 0; st < 4; ++st)
+    // FP64 MFMA A operand of the element reductions: step st, lane ln ->
+    // row ln % 16 (0: w/2, 1-3: P1 midpoint functionals) at node 4 st + ln / 16
+    const int KR = (Np + 3) / 4;
+    std::vector<double> wred(size_t(8) * 64, 0.0);
+    if (Np <= 32)
+        for (int st = 0; st < KR; ++st)
             for (int ln = 0; ln < 64; ++ln) {
                 const int row = ln % 16, nd = 4 * st + ln / 16;
                 if (row > 3 || nd >= Np) continue;
@@ -883,8 +893,10 @@ int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out,
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int> cand;
-    if (h->p.precision >= DG_FUSED_MFMA32)
-        cand = {4, 8, 16};
+    if (h->p.precision >= DG_FUSED_MFMA32) {
+        const int epw = 64 / mfma_lanes(h->p.N);
+        cand = {epw, 2 * epw, 4 * epw};
+    }
     else
         cand = {step_elems_per_block(h->p.N, engine_of(h->p.precision))};
     // The trial launches repeat the step kernel of the next tick (tick 0 of

@@ -514,14 +514,18 @@ struct MShape {
     static constexpr int Np = (N + 1) * (N + 2) / 2;
     static constexpr int Nfp = N + 1;
     static constexpr int nF = 3 * (N + 1);
+    static constexpr int LPE = mfma_lanes(N);                         // lanes per element
+    static constexpr int EPW = 64 / LPE;                              // elements per wave
+    static constexpr int NT = LPE / 16;                               // 16-node column tiles
     static constexpr int KQ = BF ? 32 : 4;                            // K per MFMA step
-    static constexpr int KV = BF ? (2 * Np + 31) & ~31 : mfma_kv(N);  // first LIFT column
+    static constexpr int KV = mfma_kv(N);                             // first LIFT column
     static constexpr int KS = BF ? (KV + nF + 31) / 32 : mfma_steps(N);
     static constexpr int SV = KV / KQ;                                // volume-only steps
     static constexpr int KSP = BF ? KS : (KS + 3) & ~3;               // FP32: steps padded to float4
     static constexpr int RL = BF ? 32 * KS : 4 * KSP;                 // row length (floats)
     static constexpr int RS = RL + 4;                                 // LDS row stride (floats)
-    static_assert(Np <= 16 && nF <= 16, "element must fit a 16-lane group");
+    static constexpr int KR = (Np + 3) / 4;                           // FP64 reduction steps
+    static_assert(Np <= LPE && nF <= LPE, "element must fit its lane group");
     static __device__ __forceinline__ int perm(int k) {
         if constexpr (BF) return ((k >> 3) & 3) * (8 * KS) + (k >> 5) * 8 + (k & 7);
         else return (k & 3) * KSP + (k >> 2);
@@ -566,9 +570,12 @@ __device__ __forceinline__ floatx4 bf16_products(const bf16x8 (&x)[P], const bf1
 // face node fn of the reference element from a 4-bit packed table (N <= 4)
 template <int N>
 __device__ __forceinline__ int face_node(int fn) {
-    static_assert(N <= 4, "3(N+1) face nodes of 4 bits must fit 64 bits");
-    constexpr unsigned long long bits = face_node_bits(N);
-    return (int)((bits >> (4 * fn)) & 15ull);
+    if constexpr (N <= 4) {   // 3(N+1) entries of 4 bits fit 64 bits
+        constexpr unsigned long long bits = face_node_bits(N);
+        return (int)((bits >> (4 * fn)) & 15ull);
+    } else {
+        return face_node_index(N, fn);
+    }
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -593,16 +600,16 @@ __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(B
 step_mfma_kernel(StepArgs a) {
     using S = MShape<N, BF>;
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KV = S::KV, KS = S::KS, SV = S::SV;
-    constexpr int KSP = S::KSP, RS = S::RS, RL = S::RL;
-    // LDS is per wave (its four elements): the X^T rows, and after they have
+    constexpr int KSP = S::KSP, RS = S::RS, RL = S::RL, LPE = S::LPE, EPW = S::EPW, NT = S::NT;
+    // LDS is per wave (its EPW elements): the X^T rows, and after they have
     // been read into registers, the FP64 node values and reductions in the
     // same bytes
     struct WaveLds {
         union {
-            float A[4][3][RS];
+            float A[EPW][3][RS];
             struct {
-                double Vd[4][3][16];   // updated h, hu, hv per node
-                double Red[4][16];     // 1-3 means, 4-12 deviations
+                double Vd[EPW][3][LPE];   // updated h, hu, hv per node
+                double Red[EPW][16];      // 1-3 means, 4-12 deviations
             } r;
         };
     };
@@ -610,18 +617,19 @@ step_mfma_kernel(StepArgs a) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int q = lane >> 4, j = lane & 15;
-    const int el = wave * 4 + q;
-    float (&sA)[4][3][RS] = lds[wave].A;
-    double (&sVd)[4][3][16] = lds[wave].r.Vd;
-    double (&sRed)[4][16] = lds[wave].r.Red;
+    const int q = lane / LPE, j = lane % LPE;
+    const int gbase = lane & ~(LPE - 1);   // first lane of the element
+    const int el = wave * EPW + q;
+    float (&sA)[EPW][3][RS] = lds[wave].A;
+    double (&sVd)[EPW][3][LPE] = lds[wave].r.Vd;
+    double (&sRed)[EPW][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = a.k_begin + blk * (4 * WPB) + el;
+    const int k = a.k_begin + blk * (EPW * WPB) + el;
     const bool live = k < a.k_end;
     const bool node = live && j < Np;
     // loads are unconditional: lanes past the last element read the last
-    // element and lane 15 (j >= Np) reads node Np - 1; their results are
-    // never stored
+    // element and lanes j >= Np read node Np - 1; their results are never
+    // stored
     const int kc = live ? k : a.k_end - 1;
     const unsigned KNp = (unsigned)a.KNp;
     const float g = a.g, hvel = a.hvel;
@@ -686,8 +694,8 @@ step_mfma_kernel(StepArgs a) {
         }
     }
 
-    const float eta0 = __shfl(eta, lane & ~15);
-    const float lo0 = __shfl(lo, lane & ~15);
+    const float eta0 = __shfl(eta, gbase);
+    const float lo0 = __shfl(lo, gbase);
     const float dlt = (eta - eta0) + (lo - lo0);
 
     // ---- X^T rows: volume fluxes (negated), zero padding
@@ -707,11 +715,11 @@ step_mfma_kernel(StepArgs a) {
     }
     // padding after the volume and after the lift columns (finite: the
     // operator is zero there)
-    for (int t = j; t < KV - 2 * Np; t += 16) {
+    for (int t = j; t < KV - 2 * Np; t += LPE) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + t)] = 0.f;
     }
-    for (int t = j; t < RL - (KV + nF); t += 16) {
+    for (int t = j; t < RL - (KV + nF); t += LPE) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + t)] = 0.f;
     }
@@ -719,25 +727,31 @@ step_mfma_kernel(StepArgs a) {
 
     // ---- volume part of the contraction on the matrix cores, issued before
     // the face flux so that it overlaps the neighbour loads
-    // A-operand row (element ar/4, field ar%4) of this wave; field row 3 is
-    // not contracted (its lanes read field 0 and their results are unused)
+    // A-operand row r = lane % 16 holds field r % 4 of element r / (4 NT) of
+    // this wave: with two column tiles every element's rows appear twice, so
+    // that tile t lands in the lanes of nodes 16 t .. 16 t + 15.  Field row 3
+    // is not contracted (its lanes read field 0, results unused).
     const int ar = lane & 15;
+    const int ae = (ar >> 2) / NT;
     const int arow = (ar & 3) == 3 ? 0 : (ar & 3);
     const int ag = lane >> 4;           // K group supplied by this lane
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF) {
         constexpr int SV4 = (SV + 3) / 4;   // float4 chunks covering the volume steps
         float av[4 * SV4];
 #pragma unroll
         for (int s4 = 0; s4 < SV4; ++s4) {
-            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][arow][ag * KSP + 4 * s4]);
+            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ae][arow][ag * KSP + 4 * s4]);
             av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
         }
-        float opB[SV];
 #pragma unroll
-        for (int s = 0; s < SV; ++s) opB[s] = ldg(a.ops.Amfma, (unsigned)(s * 64 + lane));
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int s = 0; s < SV; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], opB[s], acc, 0, 0, 0);
+            for (int s = 0; s < SV; ++s)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    av[s], ldg(a.ops.Amfma, (unsigned)((t * KS + s) * 64 + lane)), acc[t], 0, 0, 0);
     } else {
         // X and the operator split into P = BF + 1 BF16 parts; the operator
         // table holds hi, mid, lo parts (the two-part split uses hi, mid)
@@ -745,21 +759,25 @@ step_mfma_kernel(StepArgs a) {
         const bf16x8* tab = reinterpret_cast<const bf16x8*>(a.ops.Abf);
 #pragma unroll
         for (int s = 0; s < SV; ++s) {
-            const float* xp = &sA[ar >> 2][arow][ag * 8 * KS + 8 * s];
-            bf16x8 xs[P], o[P];
+            const float* xp = &sA[ae][arow][ag * 8 * KS + 8 * s];
+            bf16x8 xs[P];
             bf16_split<P>(*reinterpret_cast<const float4*>(xp), *reinterpret_cast<const float4*>(xp + 4), xs);
 #pragma unroll
-            for (int t = 0; t < P; ++t) o[t] = ldg(tab, (unsigned)(3 * (s * 64 + lane) + t));
-            acc = bf16_products<P>(xs, o, acc);
+            for (int t = 0; t < NT; ++t) {
+                bf16x8 o[P];
+#pragma unroll
+                for (int u = 0; u < P; ++u) o[u] = ldg(tab, (unsigned)(3 * ((t * KS + s) * 64 + lane) + u));
+                acc[t] = bf16_products<P>(xs, o, acc[t]);
+            }
         }
     }
 
     // ---- face node fn = j of element q: reconstructed states, LLF flux
-    const float etaM = __shfl(eta, (lane & ~15) + n);
-    const float huM = __shfl(hu, (lane & ~15) + n);
-    const float hvM = __shfl(hv, (lane & ~15) + n);
-    const float BM = __shfl(Bn, (lane & ~15) + n);
-    const float loM = __shfl(lo, (lane & ~15) + n);
+    const float etaM = __shfl(eta, gbase + n);
+    const float huM = __shfl(hu, gbase + n);
+    const float hvM = __shfl(hv, gbase + n);
+    const float BM = __shfl(Bn, gbase + n);
+    const float loM = __shfl(lo, gbase + n);
     if (nb < 0) {
         const float mn = huM * nx + hvM * ny;
         etaP = etaM;
@@ -779,7 +797,7 @@ step_mfma_kernel(StepArgs a) {
                                      fabsf(unP) + __builtin_amdgcn_sqrtf(g * hsP))
                              : 0.f;
     float lam = lamN;
-    const int fbase = (lane & ~15) + f * Nfp;
+    const int fbase = gbase + f * Nfp;
 #pragma unroll
     for (int t = 0; t < Nfp; ++t) lam = fmaxf(lam, __shfl(lamN, fbase + t));
     if (fnode) {
@@ -801,31 +819,40 @@ step_mfma_kernel(StepArgs a) {
         float af[4 * (F1 - F0)];
 #pragma unroll
         for (int s4 = F0; s4 < F1; ++s4) {
-            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ar >> 2][arow][ag * KSP + 4 * s4]);
+            const float4 v4 = *reinterpret_cast<const float4*>(&sA[ae][arow][ag * KSP + 4 * s4]);
             af[4 * (s4 - F0)] = v4.x; af[4 * (s4 - F0) + 1] = v4.y;
             af[4 * (s4 - F0) + 2] = v4.z; af[4 * (s4 - F0) + 3] = v4.w;
         }
 #pragma unroll
-        for (int s = SV; s < KS; ++s)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s - 4 * F0], ldg(a.ops.Amfma, (unsigned)(s * 64 + lane)),
-                                                       acc, 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = SV; s < KS; ++s)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    af[s - 4 * F0], ldg(a.ops.Amfma, (unsigned)((t * KS + s) * 64 + lane)), acc[t], 0, 0, 0);
     } else {
         constexpr int P = BF + 1;
         const bf16x8* tab = reinterpret_cast<const bf16x8*>(a.ops.Abf);
 #pragma unroll
         for (int s = SV; s < KS; ++s) {
-            const float* xp = &sA[ar >> 2][arow][ag * 8 * KS + 8 * s];
-            bf16x8 xs[P], o[P];
+            const float* xp = &sA[ae][arow][ag * 8 * KS + 8 * s];
+            bf16x8 xs[P];
             bf16_split<P>(*reinterpret_cast<const float4*>(xp), *reinterpret_cast<const float4*>(xp + 4), xs);
 #pragma unroll
-            for (int t = 0; t < P; ++t) o[t] = ldg(tab, (unsigned)(3 * (s * 64 + lane) + t));
-            acc = bf16_products<P>(xs, o, acc);
+            for (int t = 0; t < NT; ++t) {
+                bf16x8 o[P];
+#pragma unroll
+                for (int u = 0; u < P; ++u) o[u] = ldg(tab, (unsigned)(3 * ((t * KS + s) * 64 + lane) + u));
+                acc[t] = bf16_products<P>(xs, o, acc[t]);
+            }
         }
     }
+    // lane with node j takes column tile j / 16 (row group: its element, copy j / 16)
+    floatx4 accj = acc[0];
+    if constexpr (NT == 2) accj = j < 16 ? acc[0] : acc[1];
     float Rn[3];
-    Rn[0] = acc[0];
-    Rn[1] = acc[1] - g * dlt * dBx;
-    Rn[2] = acc[2] - g * dlt * dBy;
+    Rn[0] = accj[0];
+    Rn[1] = accj[1] - g * dlt * dBx;
+    Rn[2] = accj[2] - g * dlt * dBy;
 
     // ---- Adams-Bashforth update, RHS ring, half-step traces
     float qn[3] = {eta, hu, hv};
@@ -864,22 +891,21 @@ step_mfma_kernel(StepArgs a) {
     sVd[q][2][j] = node ? (double)qn[2] : 0.0;
     double hmin = node ? h64 : 1e300;
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, 16));
+    for (int m = LPE / 2; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, LPE));
     wave_lds_sync();
-    double wred[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) wred[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
         const int c = lane & 15;          // column: element c/4, field c%4
-        const int fc = c & 3;
+        const int ec = c >> 2, fc = c & 3;
+        const bool col = fc < 3 && ec < EPW;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const double bv = fc < 3 ? sVd[c >> 2][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
-            red = __builtin_amdgcn_mfma_f64_16x16x4f64(wred[s], bv, red, 0, 0, 0);
+        for (int s = 0; s < S::KR; ++s) {
+            const double bv = col ? sVd[ec < EPW ? ec : 0][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
+            red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red,
+                                                       0, 0, 0);
         }
         // lane 16 g + c holds row g (0: mean, 1-3: midpoint deviation g-1) of column c
-        if (fc < 3) sRed[c >> 2][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
+        if (col) sRed[ec][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
     }
     wave_lds_sync();
     // ---- positivity limiter decision (Algorithm 5.2), taken by all lanes of
@@ -1171,7 +1197,7 @@ static int check_launch(const char* what) {
 }
 
 int step_elems_per_block(int N, int engine) {
-    if (engine != ENGINE_VALU && N <= 4) return kMfmaDefaultElems;
+    if (engine != ENGINE_VALU && N <= 5) return kMfmaDefaultWaves * (64 / mfma_lanes(N));
     return 256 / ((N + 1) * (N + 2) / 2);
 }
 
@@ -1186,10 +1212,11 @@ static void dispatch(K kernel, int blocks, int threads, hipStream_t s, const Ste
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), 0, s, a);
 }
 
-// matrix-core step kernel with W waves (4 W elements) per block
+// matrix-core step kernel with W waves (EPW W elements) per block
 template <int N, int W>
 static void dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
-    const int blocks = (n + 4 * W - 1) / (4 * W);
+    constexpr int EPW = 64 / mfma_lanes(N);
+    const int blocks = (n + EPW * W - 1) / (EPW * W);
     const int bf = a.engine == ENGINE_MFMA_BF16X3 ? 1 : (a.engine == ENGINE_MFMA_BF16X6 ? 2 : 0);
     if (a.nlev > 1) {
         if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, a, e0, e1);
@@ -1206,14 +1233,17 @@ template <int N>
 static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e0, hipEvent_t e1) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
-    if constexpr (N <= 4) {
+    if constexpr (N <= 5) {
         if (a.engine != ENGINE_VALU && a.mode == MODE_FUSED) {
-            switch (epb) {
-                case 4: dispatch_mfma<N, 1>(n, s, a, e0, e1); break;
-                case 8: dispatch_mfma<N, 2>(n, s, a, e0, e1); break;
-                case 16: dispatch_mfma<N, 4>(n, s, a, e0, e1); break;
+            constexpr int EPW = 64 / mfma_lanes(N);
+            const int w = epb % EPW == 0 ? epb / EPW : 0;
+            switch (w) {
+                case 1: dispatch_mfma<N, 1>(n, s, a, e0, e1); break;
+                case 2: dispatch_mfma<N, 2>(n, s, a, e0, e1); break;
+                case 4: dispatch_mfma<N, 4>(n, s, a, e0, e1); break;
                 default:
-                    std::snprintf(g_dev_err, sizeof(g_dev_err), "elements per block %d not in {4, 8, 16}", epb);
+                    std::snprintf(g_dev_err, sizeof(g_dev_err),
+                                  "elements per block %d is not 1, 2 or 4 waves of %d elements", epb, EPW);
                     return -1;
             }
             return check_launch("step mfma kernel");

@@ -131,12 +131,17 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
                 void* ev_stop = nullptr);
 int launch_tvb(const TvbArgs& a, void* stream);
 int launch_diag(const DiagArgs& a, void* stream);
-// elements per block: matrix-core kernel 4, 8 or 16 (1, 2 or 4 waves of four
-// elements); VALU kernel floor(256 / Np) (fixed)
-constexpr int kMfmaDefaultElems = 16;
+// elements per block: matrix-core kernel 1, 2 or 4 waves of 64 / lanes
+// elements (N <= 4: 4, 8, 16; N = 5: 2, 4, 8), default 4 waves; VALU kernel
+// floor(256 / Np) (fixed)
+constexpr int kMfmaDefaultWaves = 4;
 int step_elems_per_block(int N, int engine);
 
-// K layout of the matrix-core contraction (N <= 4): Dr columns 0..Np-1, Ds
+// Lanes per element of the matrix-core kernel: 16 (Np <= 16, four elements
+// per wave) or 32 (N = 5, two elements per wave, two 16-node column tiles)
+constexpr int mfma_lanes(int N) { return (N + 1) * (N + 2) / 2 <= 16 ? 16 : 32; }
+
+// K layout of the matrix-core contraction (N <= 5): Dr columns 0..Np-1, Ds
 // columns Np..2Np-1, zero padding to mfma_kv(N) (a multiple of 4), LIFT
 // columns from mfma_kv(N); mfma_steps(N) steps of K = 4 in total, the first
 // mfma_kv(N) / 4 of them volume-only

@@ -106,10 +106,14 @@ def test_error_paths():
             dgswe.Solver([(vx, vy, tri)], 3, precision=prec, elems_per_block=bad)
         assert e.value.code == -1
     dgswe.Solver([(vx, vy, tri)], 3, precision="fused_fp32", elems_per_block=25)   # 256 // Np
-    for prec in ("fused_bf16x3", "fused_bf16x6"):     # BF16 split contraction: N <= 4
-        dgswe.Solver([(vx, vy, tri)], 4, precision=prec)
+    for prec in ("fused_mfma32", "fused_bf16x3", "fused_bf16x6"):   # matrix cores: N <= 5
+        dgswe.Solver([(vx, vy, tri)], 5, precision=prec)
+        dgswe.Solver([(vx, vy, tri)], 5, precision=prec, elems_per_block=2)   # 32-lane elements
         with pytest.raises(dgswe.DGError) as e:
-            dgswe.Solver([(vx, vy, tri)], 5, precision=prec)
+            dgswe.Solver([(vx, vy, tri)], 5, precision=prec, elems_per_block=16)
+        assert e.value.code == -1
+        with pytest.raises(dgswe.DGError) as e:
+            dgswe.Solver([(vx, vy, tri)], 6, precision=prec)
         assert e.value.code == -1
     s = dgswe.Solver([(vx, vy, np.array([[0, 1, 3], [0, 3, 2]]))], 2)
     with pytest.raises(dgswe.DGError) as e:           # no state to tune on
