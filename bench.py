@@ -1,17 +1,21 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
-One step = one single-rate AB3 step of the whole path: right-hand side
-(volume + well-balanced LLF surface term + lift), AB update, positivity
-limiter, TVB limiter.  Workload: 256x256x2 jittered triangles on the unit
-square (131072 elements), N = 4 (15 nodes), sloping beach with eight bumps,
-still level 0.5, Gaussian hump, wet/dry, CFL 0.2; inputs are resident in HBM
-before the timed region.
+One step = one single-rate AB3 step of the whole path (multi-rate: one
+coarse step, 2^(L-1) ticks): right-hand side (volume + well-balanced LLF
+surface term + lift), AB update, positivity limiter, TVB limiter.  Default
+workload (the bench line): 256x256x2 jittered triangles on the unit square
+(131072 elements), N = 4 (15 nodes), sloping beach with eight bumps, still
+level 0.5, Gaussian hump, wet/dry, CFL 0.2.  --workload c3 / c4 / c5 run the
+graded multi-rate mesh (4 levels, N = 3), the 1,048,576-element N = 5 mesh
+and the 64-instance ensemble instead.  Inputs are resident in HBM before the
+timed region.
 
 Prints one JSON line: node-updates/s (value), the roofline of the fused step
 kernel (algorithmic bytes over its HIP-event time, against 8 TB/s), the
 plain (unfused) FP32 path on the same GPU, relative L2 against the FP64
-oracle after the configured 500 steps (when the stored oracle samples are
-present), and the oracle's own throughput on this host's cores.
+oracle after the configured 500 steps of the default workload (when the
+stored oracle samples are present), and the oracle's own throughput on this
+host's cores (default workload).
 """
 from __future__ import annotations
 
@@ -74,20 +78,31 @@ def step_kernel_bytes(Np: int) -> int:
 
 
 def make_solver(wl, precision, use_graph=1, tune=False):
-    """Solver on the workload's first instance, state set and prepared; with
-    tune, the launch shape of the step kernel is picked by the library's
-    autotuner (outside any timed region)."""
+    """Solver over all instances of the workload, state set and prepared;
+    with tune, the launch shape of the step kernel is picked by the
+    library's autotuner (outside any timed region)."""
     from paper_1403_1661_amd import dgswe
-    ins = wl.instances[0]
-    s = dgswe.Solver([(ins.vx, ins.vy, ins.etov)], wl.N, g=wl.g, cfl=wl.cfl,
-                     precision=precision, use_graph=use_graph)
+    s = dgswe.Solver([(i.vx, i.vy, i.etov) for i in wl.instances], wl.N, g=wl.g, cfl=wl.cfl,
+                     precision=precision, use_graph=use_graph, max_levels=wl.max_levels)
     s.bind("cuda:0")
-    x, y = s.node_coords(0)
-    s.set_bathymetry(0, ins.bathymetry(x, y))
-    s.set_state(0, *ins.initial(x, y))
+    for j, ins in enumerate(wl.instances):
+        x, y = s.node_coords(j)
+        s.set_bathymetry(j, ins.bathymetry(x, y))
+        s.set_state(j, *ins.initial(x, y))
     s.prepare()
     s.tuning = s.autotune(reps=10) if tune else None
     return s
+
+
+def node_updates_per_step(s, wl) -> int:
+    """Node-updates of one (coarse) step: every element advances 2^(L-l)
+    times on level l of L."""
+    total = 0
+    for j in range(len(wl.instances)):
+        lev, _ = s.levels(j)
+        L = int(lev.max())
+        total += int(np.sum(2 ** (L - lev.astype(np.int64)))) * wl.Np
+    return total
 
 
 def timed(s, steps, torch):
@@ -136,11 +151,25 @@ def rel_l2_vs_golden(s, wl):
     return out
 
 
+WORKLOADS = {
+    "c2": ("256x256x2 jittered triangles (131072) on [0,1]^2, N=4 (Np=15), beach 0.8x + 8 bumps, "
+           "still level 0.5, hump 0.05, wet/dry PP+TVB, single-rate AB3 at CFL 0.2, 500 configured steps",
+           480, 20),
+    "c3": ("graded band mesh of [0,4]x[0,1] (54*2^b cells per unit in band b, 496098 triangles), N=3, "
+           "B=0.9(x/4)^2, N-wave, 4 MRAB levels, 100 configured coarse steps", 96, 4),
+    "c4": ("1024x512x2 jittered triangles (1048576) on [0,2]x[0,1], N=5 (Np=21), 16 Fourier modes, "
+           "fully wet, single-rate AB3, 300 configured steps", 280, 20),
+    "c5": ("64 jittered unit squares, 10k-200k triangles each (log-uniform), N=3, beach + hump, "
+           "wet/dry PP+TVB, CFL 0.2, 200 configured steps each, one batched solver", 180, 20),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=480)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--precision", default="fused_mfma32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -159,66 +188,72 @@ def main():
     import torch
     import workloads as W
     assert torch.cuda.is_available(), "needs a GPU"
-    wl = W.c2()
-    K = wl.n_elements
+    desc, d_steps, d_warm = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else d_steps
+    warmup = args.warmup if args.warmup is not None else d_warm
+    wl = getattr(W, args.workload)()
     Np = wl.Np
 
     s = make_solver(wl, args.precision, use_graph=0 if args.no_graph else 1, tune=not args.no_tune)
-    tuned = min(s.tuning, key=lambda t: t[1])[0] if s.tuning else None
-    s.advance(args.warmup)
+    tuning = s.tuning
+    tuned = min(tuning, key=lambda t: t[1])[0] if tuning else None
+    per_step = node_updates_per_step(s, wl)
+    s.advance(warmup)
     torch.cuda.synchronize()
-    t = timed(s, args.steps, torch)
-    ms = 1e3 * t / args.steps
-    value = K * Np * args.steps / t
+    t = timed(s, steps, torch)
+    ms = 1e3 * t / steps
+    value = per_step * steps / t
     accuracy = None
-    if args.warmup + args.steps == wl.steps:
+    if args.workload == "c2" and warmup + steps == wl.steps:
         accuracy = rel_l2_vs_golden(s, wl)
     diag = s.diagnostics(0)
 
-    # per-launch duration of the fused step kernel: HIP events recorded on the
-    # stream it runs on, over a second region of the same length
+    # per-launch duration of the fused step kernel: start/stop events of each
+    # launch on the stream it runs on, over a second region of the same length
     s.set_profiling(True)
-    s.advance(args.steps)
+    s.advance(steps)
     torch.cuda.synchronize()
     avg_us, launches, elems = s.kernel_timing()
     s.set_profiling(False)
     bytes_launch = step_kernel_bytes(Np) * elems
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    del s
 
     plain = None
     if not args.no_plain and args.precision != "plain_fp32":
         p = make_solver(wl, "plain_fp32")
-        p.advance(args.warmup)
-        tp = timed(p, args.steps, torch)
-        plain = {"value": K * Np * args.steps / tp, "ms_per_step": 1e3 * tp / args.steps}
+        p.advance(warmup)
+        tp = timed(p, steps, torch)
+        plain = {"value": per_step * steps / tp, "ms_per_step": 1e3 * tp / steps}
         del p
 
+    kname = "step_mfma_kernel" if args.precision in ("fused_mfma32", "fused_bf16x3", "fused_bf16x6") \
+        else "step_kernel"
+    traffic = measured_traffic(args.precision) if args.workload == "c2" else None
     out = {
         "metric": "DG node-updates/s + HBM GB/s; FP32/BF16-split vs FP32 plain at rel-L2 1e-5",
         "value": value,
         "unit": "node-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "256x256x2 jittered triangles (131072) on [0,1]^2, N=4 (Np=15), "
-                               "beach 0.8x + 8 bumps, still level 0.5, hump 0.05, wet/dry PP+TVB, "
-                               "single-rate AB3 at CFL 0.2, 500 configured steps",
-                   "elements": K, "N": wl.N, "path": args.precision, "parallelism": "single GPU",
-                   "elems_per_block": tuned,
-                   "autotune_us": {str(e): round(us, 2) for e, us in s.tuning} if s.tuning else None},
-        "hbm_gbps_algorithmic_step": step_kernel_bytes(Np) * K * args.steps / t / 1e9,
+        "config": {"workload": desc, "name": args.workload,
+                   "elements": int(sum(i.etov.shape[0] for i in wl.instances)),
+                   "instances": len(wl.instances), "N": wl.N, "path": args.precision,
+                   "parallelism": "single GPU", "elems_per_block": tuned,
+                   "autotune_us": {str(e): round(us, 2) for e, us in tuning} if tuning else None},
+        "hbm_gbps_algorithmic_step": step_kernel_bytes(Np) * (per_step / Np) * steps / t / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
-                     "kernel": f"{'step_mfma_kernel' if args.precision == 'fused_mfma32' else 'step_kernel'}"
-                               f"<{wl.N}> (fused RHS + AB3 + positivity)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"{kname}<{wl.N}> (fused RHS + AB3 + positivity)",
                      "kernel_avg_us": avg_us, "launches_timed": launches,
-                     "bytes_per_launch": bytes_launch},
+                     "elements_per_launch": elems, "bytes_per_launch": bytes_launch},
         "plain_fp32": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "rel_l2_vs_oracle": accuracy,
@@ -226,7 +261,7 @@ def main():
                         "pp_counts": diag["pp_counts"], "tvb_counts": diag["tvb_counts"],
                         "negative_means": diag["negative_means"]},
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 

@@ -222,9 +222,13 @@ int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes);
 int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream);
 int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* stream);
 
-/* Device timing of the last dg_advance when the solver was created with
- * profiling on: average duration (microseconds) of the dominant fused kernel
- * measured with HIP events on the stream it runs on. */
+/* Device timing of the step kernel.  dg_set_profiling(h, 1) starts a timed
+ * region (and resets it): every later step-kernel launch of dg_advance runs
+ * eagerly with start/stop events stamped by its dispatch, on the stream it
+ * runs on.  dg_kernel_timing returns the average duration in microseconds,
+ * the number of timed launches and the average number of elements per timed
+ * launch (all elements single rate; the active levels of each tick with
+ * multi-rate stepping).  Synchronises on the recorded events. */
 int32_t dg_set_profiling(dg_solver* h, int32_t on);
 int32_t dg_kernel_timing(const dg_solver* h, double* avg_us, int64_t* launches,
                          int64_t* elements_per_launch);

@@ -728,6 +728,7 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
             h->prof_events.push_back({e0, e1});
         }
         ev = &h->prof_events[h->prof_used++];
+        h->prof_elems += a.k_end - a.k_begin;
     }
     if (limit_only) {
         a.mode = MODE_LIMIT_ONLY;
@@ -1111,6 +1112,7 @@ int32_t dg_set_profiling(dg_solver* h, int32_t on) {
     if (!h) return fail(DG_EINVAL, "null handle");
     h->profiling = on != 0;
     h->prof_used = 0;
+    h->prof_elems = 0;
     return DG_OK;
 }
 
@@ -1126,7 +1128,7 @@ int32_t dg_kernel_timing(const dg_solver* hc, double* avg_us, int64_t* launches,
     }
     if (avg_us) *avg_us = h->prof_used ? tot * 1000.0 / h->prof_used : 0.0;
     if (launches) *launches = (int64_t)h->prof_used;
-    if (elems) *elems = h->K;
+    if (elems) *elems = h->prof_used ? (h->prof_elems + (long long)h->prof_used / 2) / (long long)h->prof_used : 0;
     return DG_OK;
 }
 
