@@ -310,6 +310,9 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         st[12] = float(p->tvb_M * m.dk[k] * m.dk[k]);
         std::memcpy(&st[13], &pairs, 4);
     }
+    // the kernels address nodal arrays with 32-bit byte offsets (4 fields)
+    if (16.0 * double(h->K) * double(h->Np) >= 4294967296.0)
+        return fail(DG_EINVAL, "too many nodes: 16 K Np must stay below 2^32 bytes");
     compute_layout(h.get());
     *out = h.release();
     return DG_OK;
@@ -708,6 +711,16 @@ static TvbArgs tvb_args(dg_solver* h, const StepArgs& sa) {
 }
 
 // Enqueue one tick (single rate: one step) on stream s.
+// single-rate buffers of level 0 resolved for the kernels
+static void resolve_single_rate(dg_solver* h, StepArgs& a) {
+    const LevelArgs& l0 = a.lev[0];
+    a.q_in = a.Q[l0.parity];
+    a.q_out = a.Q[1 - l0.parity];
+    a.r_now = a.R[l0.slot[0]];
+    a.r_prev1 = a.R[l0.slot[1]];
+    a.r_prev2 = a.R[l0.slot[2]];
+}
+
 static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) {
     int m = 1;
     if (!limit_only)
@@ -716,6 +729,7 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
         m = h->L;
     StepArgs a = base_step_args(h);
     fill_levels(h, a.lev, m, limit_only);
+    resolve_single_rate(h, a);
     a.k_begin = 0;
     a.k_end = h->lev_end[m - 1];
     const bool prof = h->profiling && !limit_only;
@@ -912,6 +926,7 @@ int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out,
     HIPCHECK(hipMemcpy(&counter, h->ws + l.counters, 8, hipMemcpyDeviceToHost));
     StepArgs a = base_step_args(h);
     fill_levels(h, a.lev, h->L, false);
+    resolve_single_rate(h, a);
     a.k_begin = 0;
     a.k_end = h->lev_end[h->L - 1];
     a.mode = h->p.precision == DG_PLAIN_FP32 ? MODE_RHS_ONLY : MODE_FUSED;

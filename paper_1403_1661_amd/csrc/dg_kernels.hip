@@ -595,6 +595,22 @@ __device__ __forceinline__ void stg(T* base, unsigned i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
 }
 
+// Raw buffer view of an FP32 array: a resource descriptor in scalar
+// registers and 32-bit byte offsets (element offset in a vector register,
+// field offset in a scalar one), so no 64-bit address arithmetic per lane;
+// accesses beyond `bytes` read 0 and write nothing.
+struct BufF32 {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufF32(const float* p, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, (int)bytes, 0x00020000)) {}
+    __device__ __forceinline__ float ld(unsigned i, unsigned field_bytes) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), (int)field_bytes, 0));
+    }
+    __device__ __forceinline__ void st(unsigned i, unsigned field_bytes, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(i * 4u), (int)field_bytes, 0);
+    }
+};
+
 template <int N, bool MULTI, int WPB, int BF>
 __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(BF == 2 ? (MULTI ? 4 : 5) : (BF ? (MULTI ? 5 : 6) : (MULTI ? 6 : 7)), 8)))
 step_mfma_kernel(StepArgs a) {
@@ -642,20 +658,44 @@ step_mfma_kernel(StepArgs a) {
     const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * kc);   // rx, ry, sx, sy
     const float dtmin = ldg(a.geo, 16u * kc + 14u);
     const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
-    const float eta = ldg(Qi, idx);
-    const float hu = ldg(Qi + KNp, idx);
-    const float hv = ldg(Qi + 2 * (size_t)KNp, idx);
-    const float lo = ldg(Qi + 3 * (size_t)KNp, idx);
-    const float Bn = ldg(a.B, idx);
-    const float dBx = ldg(a.dB, idx), dBy = ldg(a.dB + KNp, idx);   // static bed gradient
+    // single rate: buffer views of the level's arrays (byte offsets < 2^32,
+    // checked by the host); multi-rate picks its buffers per element
+    const unsigned FB = 4u * KNp;   // bytes of one nodal field
+    const BufF32 bQi(a.q_in, 4u * FB), bQo(a.q_out, 4u * FB), bB(a.B, FB), bdB(a.dB, 2u * FB);
+    const BufF32 bR0(a.r_now, 3u * FB), bR1(a.r_prev1, 3u * FB), bR2(a.r_prev2, 3u * FB);
+    float eta, hu, hv, lo, Bn, dBx, dBy;
     float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
-    if (L.ab[1] != 0.f) {
-        const float* R1 = a.R[L.slot[1]];
-        r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
-    }
-    if (L.ab[2] != 0.f) {
-        const float* R2 = a.R[L.slot[2]];
-        r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
+    if constexpr (!MULTI) {
+        eta = bQi.ld(idx, 0);
+        hu = bQi.ld(idx, FB);
+        hv = bQi.ld(idx, 2u * FB);
+        lo = bQi.ld(idx, 3u * FB);
+        Bn = bB.ld(idx, 0);
+        dBx = bdB.ld(idx, 0);   // static bed gradient
+        dBy = bdB.ld(idx, FB);
+        // the RHS history is read unconditionally (slots hold zeros or
+        // finite RHS values) and weighted by the level's AB coefficients
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r1[c] = bR1.ld(idx, c * FB);
+            r2[c] = bR2.ld(idx, c * FB);
+        }
+    } else {
+        eta = ldg(Qi, idx);
+        hu = ldg(Qi + KNp, idx);
+        hv = ldg(Qi + 2 * (size_t)KNp, idx);
+        lo = ldg(Qi + 3 * (size_t)KNp, idx);
+        Bn = ldg(a.B, idx);
+        dBx = ldg(a.dB, idx);
+        dBy = ldg(a.dB + KNp, idx);
+        if (L.ab[1] != 0.f) {
+            const float* R1 = a.R[L.slot[1]];
+            r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
+        }
+        if (L.ab[2] != 0.f) {
+            const float* R2 = a.R[L.slot[2]];
+            r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
+        }
     }
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
@@ -670,7 +710,7 @@ step_mfma_kernel(StepArgs a) {
     const int f2 = nb >= 0 ? (cn.w >> (2 * f)) & 3 : f;
     const int nbc = nb >= 0 ? nb : kc;
     const unsigned id2 = (unsigned)nbc * Np + face_node<N>(f2 * Nfp + (Nfp - 1 - jj));
-    float BP = ldg(a.B, id2);
+    float BP = MULTI ? ldg(a.B, id2) : bB.ld(id2, 0);
     float etaP, huP, hvP, loP = 0.f;
     {
         const float* Q2 = Qi;
@@ -680,7 +720,12 @@ step_mfma_kernel(StepArgs a) {
             Q2 = a.Q[L2.parity];
             from_half = !L2.active && a.half != nullptr;
         }
-        if (!from_half) {
+        if (!MULTI) {
+            etaP = bQi.ld(id2, 0);
+            huP = bQi.ld(id2, FB);
+            hvP = bQi.ld(id2, 2u * FB);
+            loP = bQi.ld(id2, 3u * FB);
+        } else if (!from_half) {
             etaP = ldg(Q2, id2);
             huP = ldg(Q2 + KNp, id2);
             hvP = ldg(Q2 + 2 * (size_t)KNp, id2);
@@ -858,10 +903,15 @@ step_mfma_kernel(StepArgs a) {
     float qn[3] = {eta, hu, hv};
     float qlo = lo;
     if (node) {
-        float* R0 = a.R[L.slot[0]];
-        stg(R0, idx, Rn[0]);
-        stg(R0 + KNp, idx, Rn[1]);
-        stg(R0 + 2 * (size_t)KNp, idx, Rn[2]);
+        if constexpr (!MULTI) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
+        } else {
+            float* R0 = a.R[L.slot[0]];
+            stg(R0, idx, Rn[0]);
+            stg(R0 + KNp, idx, Rn[1]);
+            stg(R0 + 2 * (size_t)KNp, idx, Rn[2]);
+        }
         const float dt = dtmin * L.scale;
         const float q0[3] = {eta, hu, hv};
         const float q0lo[3] = {lo, 0.f, 0.f};
@@ -960,11 +1010,18 @@ step_mfma_kernel(StepArgs a) {
                 out[c] = (float)val;
         }
     }
-    float* Qo = a.Q[1 - L.parity];
-    stg(Qo, idx, out[0]);
-    stg(Qo + KNp, idx, out[1]);
-    stg(Qo + 2 * (size_t)KNp, idx, out[2]);
-    stg(Qo + 3 * (size_t)KNp, idx, olo);
+    if constexpr (!MULTI) {
+        bQo.st(idx, 0, out[0]);
+        bQo.st(idx, FB, out[1]);
+        bQo.st(idx, 2u * FB, out[2]);
+        bQo.st(idx, 3u * FB, olo);
+    } else {
+        float* Qo = a.Q[1 - L.parity];
+        stg(Qo, idx, out[0]);
+        stg(Qo + KNp, idx, out[1]);
+        stg(Qo + 2 * (size_t)KNp, idx, out[2]);
+        stg(Qo + 3 * (size_t)KNp, idx, olo);
+    }
 }
 
 // ---------------------------------------------------------------------------

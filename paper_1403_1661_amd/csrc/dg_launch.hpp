@@ -79,6 +79,13 @@ struct StepArgs {
     const float* B;        // [K*Np]
     const float* dB;       // [2][K*Np] dB/dx, dB/dy at the nodes (static, from FP64 on the host)
     float* R[3];           // ring slots [3][K*Np]
+    // single rate: the level's buffers resolved on the host (state in / out,
+    // RHS slots of R^n, R^{n-1}, R^{n-2})
+    const float* q_in;
+    float* q_out;
+    float* r_now;
+    const float* r_prev1;
+    const float* r_prev2;
     float* half;           // [3][K*3Nfp] half-step face traces (multi-rate) or null
     const float* geo;      // [K][16]
     const int* conn;       // [K][4]
