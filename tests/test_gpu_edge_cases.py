@@ -1,0 +1,106 @@
+"""Edge cases of the HIP path against the FP64 oracle: meshes smaller than one
+block of the step kernels (1, 2 and 7 elements: every launch is ragged and
+the clamped loads of the matrix-core kernel serve lanes past the last
+element), an ensemble of such ragged instances, a fully dry domain (every
+element takes the dry branch of Algorithm 5.2 and the TVB skip rule), and
+orders 1 and 5 on the smallest meshes."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import flag_flips, gpu_solver, log, oracle_solver, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain_fp32", "fused_fp32", "fused_mfma32"]
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _bed(x, y):
+    return W.on_bed_grid(0.3 * np.asarray(x) + 0.1 * np.asarray(y))
+
+
+def _tiny(n_cells_x: int, n_cells_y: int, split_one: bool = False):
+    """Triangles of a small structured patch; split_one keeps a single
+    triangle of the first cell."""
+    vx, vy, etov = W.structured_mesh(n_cells_x, n_cells_y, 0.0, 1.0, 0.0, 1.0)
+    if split_one:
+        etov = etov[:1]
+    return vx, vy, etov
+
+
+def _hump(x, y):
+    eta = 1.0 + 0.05 * np.exp(-20.0 * ((x - 0.4) ** 2 + (y - 0.3) ** 2))
+    h = eta - _bed(x, y)
+    return h, np.zeros_like(h), np.zeros_like(h)
+
+
+def _workload(meshes, N, init=_hump, steps=20):
+    insts = [W.Instance(vx, vy, ev, _bed, init, f"tiny{i}") for i, (vx, vy, ev) in enumerate(meshes)]
+    return W.Workload("tiny", N, insts, steps=steps, cfl=0.3)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("N,shape", [(4, (1, 1, True)), (4, (1, 1, False)), (3, (2, 2, False)),
+                                     (1, (1, 1, True)), (5, (1, 1, False)), (5, (2, 1, False))])
+def test_tiny_meshes(path, N, shape):
+    _require_gpu()
+    wl = _workload([_tiny(*shape)], N)
+    K = wl.n_elements
+    g = gpu_solver(wl, precision=path)
+    o = oracle_solver(wl)
+    g.advance(wl.steps)
+    o.run(wl.steps)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    log(f"[tiny] {path} N={N} K={K} relL2 h={err['h']:.3e} m={err['m']:.3e}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert flag_flips(g.flags(0), o.flags) == (0, 0)
+
+
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+def test_ragged_ensemble(path):
+    """Instances of 1, 2, 7 and 18 elements advanced together: element
+    blocks straddle instance boundaries."""
+    _require_gpu()
+    vx, vy, ev = _tiny(3, 3)
+    meshes = [_tiny(1, 1, True), _tiny(1, 1), (vx, vy, ev[:7]), _tiny(3, 3)]
+    wl = _workload(meshes, 4)
+    g = gpu_solver(wl, precision=path)
+    g.advance(wl.steps)
+    for i in range(len(meshes)):
+        o = oracle_solver(wl, inst=i)
+        o.run(wl.steps)
+        err = rel_l2(o, np.stack(g.get_state(i)), o.q)
+        log(f"[ragged] {path} inst {i} K={meshes[i][2].shape[0]} relL2 h={err['h']:.3e} m={err['m']:.3e}")
+        assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_all_dry_domain(path):
+    """The bed is above the still level everywhere: every element is dry, the
+    state stays exactly zero depth and momentum, the flags say dry and
+    skipped, and nothing becomes non-finite."""
+    _require_gpu()
+
+    def dry(x, y):
+        z = np.zeros_like(np.asarray(x, dtype=np.float64))
+        return z, z.copy(), z.copy()
+
+    vx, vy, ev = W.structured_mesh(6, 5, 0.0, 1.0, 0.0, 1.0)
+    wl = _workload([(vx, vy, ev)], 3, init=dry)
+    g = gpu_solver(wl, precision=path)
+    g.advance(wl.steps)
+    h, hu, hv = g.get_state(0)
+    assert np.all(np.isfinite(h)) and np.all(h == 0.0)
+    assert np.all(hu == 0.0) and np.all(hv == 0.0)
+    f = g.flags(0)
+    assert np.all((f & 3) == 2) and np.all((f >> 2) == 0)
+    d = g.diagnostics(0)
+    assert d["mass"] == 0.0 and d["pp_counts"][2] == wl.n_elements
