@@ -313,6 +313,10 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
     // the kernels address nodal arrays with 32-bit byte offsets (4 fields)
     if (16.0 * double(h->K) * double(h->Np) >= 4294967296.0)
         return fail(DG_EINVAL, "too many nodes: 16 K Np must stay below 2^32 bytes");
+    // multi-rate: one view spans both state buffers, another the half-step traces
+    if (h->L > 1 && (32.0 * double(h->K) * double(h->Np) + 512.0 >= 4294967296.0 ||
+                     12.0 * double(h->K) * double(h->nF) >= 4294967296.0))
+        return fail(DG_EINVAL, "too many nodes for multi-rate: 32 K Np and 12 K 3(N+1) must stay below 2^32 bytes");
     compute_layout(h.get());
     *out = h.release();
     return DG_OK;

@@ -606,6 +606,9 @@ struct BufF32 {
     __device__ __forceinline__ float ld(unsigned i, unsigned field_bytes) const {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), (int)field_bytes, 0));
     }
+    __device__ __forceinline__ float ldb(unsigned byte_off, unsigned field_bytes) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)field_bytes, 0));
+    }
     __device__ __forceinline__ void st(unsigned i, unsigned field_bytes, float v) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(i * 4u), (int)field_bytes, 0);
     }
@@ -640,62 +643,55 @@ step_mfma_kernel(StepArgs a) {
     double (&sVd)[EPW][3][LPE] = lds[wave].r.Vd;
     double (&sRed)[EPW][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = a.k_begin + blk * (EPW * WPB) + el;
-    const bool live = k < a.k_end;
+    // multi-rate: the block's level (uniform) from the launcher's cut of the
+    // element range into whole blocks per level
+    int lv = 0;
+    if constexpr (MULTI) {
+#pragma unroll
+        for (int t = 1; t < kMaxLevels; ++t) lv += (t < a.nlev && blk >= a.seg_block[t]) ? 1 : 0;
+    }
+    const LevelArgs L = a.lev[lv];
+    const int sbeg = MULTI ? a.seg_begin[lv] : a.k_begin, send = MULTI ? a.seg_end[lv] : a.k_end;
+    const int k = sbeg + (blk - (MULTI ? a.seg_block[lv] : 0)) * (EPW * WPB) + el;
+    const bool live = k < send;
     const bool node = live && j < Np;
-    // loads are unconditional: lanes past the last element read the last
-    // element and lanes j >= Np read node Np - 1; their results are never
-    // stored
-    const int kc = live ? k : a.k_end - 1;
+    // loads are unconditional: lanes past the last element of the block's
+    // range read that element and lanes j >= Np read node Np - 1; their
+    // results are never stored
+    const int kc = live ? k : send - 1;
     const unsigned KNp = (unsigned)a.KNp;
     const float g = a.g, hvel = a.hvel;
     const unsigned idx = (unsigned)kc * Np + (j < Np ? j : Np - 1);
 
     // ---- independent global loads first
-    LevelArgs L = a.lev[0];
-    if (MULTI) L = pick_level(a, level_of(a, kc));
-    const float* Qi = a.Q[L.parity];
     const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * kc);   // rx, ry, sx, sy
     const float dtmin = ldg(a.geo, 16u * kc + 14u);
     const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
-    // single rate: buffer views of the level's arrays (byte offsets < 2^32,
-    // checked by the host); multi-rate picks its buffers per element
+    // buffer views of the block's level arrays (byte offsets < 2^32, checked
+    // by the host): resolved on the host for single rate, from the level's
+    // parity and ring slots for multi-rate
     const unsigned FB = 4u * KNp;   // bytes of one nodal field
-    const BufF32 bQi(a.q_in, 4u * FB), bQo(a.q_out, 4u * FB), bB(a.B, FB), bdB(a.dB, 2u * FB);
-    const BufF32 bR0(a.r_now, 3u * FB), bR1(a.r_prev1, 3u * FB), bR2(a.r_prev2, 3u * FB);
-    float eta, hu, hv, lo, Bn, dBx, dBy;
-    float r1[3] = {0.f, 0.f, 0.f}, r2[3] = {0.f, 0.f, 0.f};
-    if constexpr (!MULTI) {
-        eta = bQi.ld(idx, 0);
-        hu = bQi.ld(idx, FB);
-        hv = bQi.ld(idx, 2u * FB);
-        lo = bQi.ld(idx, 3u * FB);
-        Bn = bB.ld(idx, 0);
-        dBx = bdB.ld(idx, 0);   // static bed gradient
-        dBy = bdB.ld(idx, FB);
-        // the RHS history is read unconditionally (slots hold zeros or
-        // finite RHS values) and weighted by the level's AB coefficients
+    const float* q_in = MULTI ? a.Q[L.parity] : a.q_in;
+    float* q_out = MULTI ? a.Q[1 - L.parity] : a.q_out;
+    float* r_now = MULTI ? a.R[L.slot[0]] : a.r_now;
+    const float* r_prev1 = MULTI ? a.R[L.slot[1]] : a.r_prev1;
+    const float* r_prev2 = MULTI ? a.R[L.slot[2]] : a.r_prev2;
+    const BufF32 bQi(q_in, 4u * FB), bQo(q_out, 4u * FB), bB(a.B, FB), bdB(a.dB, 2u * FB);
+    const BufF32 bR0(r_now, 3u * FB), bR1(r_prev1, 3u * FB), bR2(r_prev2, 3u * FB);
+    float r1[3], r2[3];
+    const float eta = bQi.ld(idx, 0);
+    const float hu = bQi.ld(idx, FB);
+    const float hv = bQi.ld(idx, 2u * FB);
+    const float lo = bQi.ld(idx, 3u * FB);
+    const float Bn = bB.ld(idx, 0);
+    const float dBx = bdB.ld(idx, 0);   // static bed gradient
+    const float dBy = bdB.ld(idx, FB);
+    // the RHS history is read unconditionally (slots hold zeros or finite RHS
+    // values) and weighted by the level's AB coefficients
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            r1[c] = bR1.ld(idx, c * FB);
-            r2[c] = bR2.ld(idx, c * FB);
-        }
-    } else {
-        eta = ldg(Qi, idx);
-        hu = ldg(Qi + KNp, idx);
-        hv = ldg(Qi + 2 * (size_t)KNp, idx);
-        lo = ldg(Qi + 3 * (size_t)KNp, idx);
-        Bn = ldg(a.B, idx);
-        dBx = ldg(a.dB, idx);
-        dBy = ldg(a.dB + KNp, idx);
-        if (L.ab[1] != 0.f) {
-            const float* R1 = a.R[L.slot[1]];
-            r1[0] = ldg(R1, idx); r1[1] = ldg(R1 + KNp, idx); r1[2] = ldg(R1 + 2 * (size_t)KNp, idx);
-        }
-        if (L.ab[2] != 0.f) {
-            const float* R2 = a.R[L.slot[2]];
-            r2[0] = ldg(R2, idx); r2[1] = ldg(R2 + KNp, idx); r2[2] = ldg(R2 + 2 * (size_t)KNp, idx);
-        }
+    for (int c = 0; c < 3; ++c) {
+        r1[c] = bR1.ld(idx, c * FB);
+        r2[c] = bR2.ld(idx, c * FB);
     }
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
@@ -710,32 +706,32 @@ step_mfma_kernel(StepArgs a) {
     const int f2 = nb >= 0 ? (cn.w >> (2 * f)) & 3 : f;
     const int nbc = nb >= 0 ? nb : kc;
     const unsigned id2 = (unsigned)nbc * Np + face_node<N>(f2 * Nfp + (Nfp - 1 - jj));
-    float BP = MULTI ? ldg(a.B, id2) : bB.ld(id2, 0);
+    float BP = bB.ld(id2, 0);
     float etaP, huP, hvP, loP = 0.f;
-    {
-        const float* Q2 = Qi;
-        bool from_half = false;
-        if (MULTI) {
-            const LevelArgs L2 = pick_level(a, level_of(a, nbc));
-            Q2 = a.Q[L2.parity];
-            from_half = !L2.active && a.half != nullptr;
-        }
-        if (!MULTI) {
-            etaP = bQi.ld(id2, 0);
-            huP = bQi.ld(id2, FB);
-            hvP = bQi.ld(id2, 2u * FB);
-            loP = bQi.ld(id2, 3u * FB);
-        } else if (!from_half) {
-            etaP = ldg(Q2, id2);
-            huP = ldg(Q2 + KNp, id2);
-            hvP = ldg(Q2 + 2 * (size_t)KNp, id2);
-            loP = ldg(Q2 + 3 * (size_t)KNp, id2);
+    const unsigned HB = 4u * (unsigned)a.KnF;   // bytes of one half-trace field
+    const BufF32 bH(a.half, 3u * HB);
+    if constexpr (!MULTI) {
+        etaP = bQi.ld(id2, 0);
+        huP = bQi.ld(id2, FB);
+        hvP = bQi.ld(id2, 2u * FB);
+        loP = bQi.ld(id2, 3u * FB);
+    } else {
+        // the neighbour's level: its state buffer (one view spans both
+        // parities) or, when it does not step at this tick, its half-step
+        // traces
+        const int l2 = level_of(a, nbc);
+        if (((a.active_bits >> l2) & 1u) || a.half == nullptr) {
+            const BufF32 bQ2(a.Q[0], a.q_pair_bytes + 4u * FB);
+            const unsigned off = id2 * 4u + (((a.parity_bits >> l2) & 1u) ? a.q_pair_bytes : 0u);
+            etaP = bQ2.ldb(off, 0);
+            huP = bQ2.ldb(off, FB);
+            hvP = bQ2.ldb(off, 2u * FB);
+            loP = bQ2.ldb(off, 3u * FB);
         } else {
             const unsigned hid = (unsigned)nbc * nF + f2 * Nfp + (Nfp - 1 - jj);
-            const unsigned KnF = (unsigned)a.KnF;
-            etaP = ldg(a.half, hid);
-            huP = ldg(a.half + KnF, hid);
-            hvP = ldg(a.half + 2 * (size_t)KnF, hid);
+            etaP = bH.ld(hid, 0);
+            huP = bH.ld(hid, HB);
+            hvP = bH.ld(hid, 2u * HB);
         }
     }
 
@@ -903,15 +899,8 @@ step_mfma_kernel(StepArgs a) {
     float qn[3] = {eta, hu, hv};
     float qlo = lo;
     if (node) {
-        if constexpr (!MULTI) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
-        } else {
-            float* R0 = a.R[L.slot[0]];
-            stg(R0, idx, Rn[0]);
-            stg(R0 + KNp, idx, Rn[1]);
-            stg(R0 + 2 * (size_t)KNp, idx, Rn[2]);
-        }
+        for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
         const float dt = dtmin * L.scale;
         const float q0[3] = {eta, hu, hv};
         const float q0lo[3] = {lo, 0.f, 0.f};
@@ -920,7 +909,6 @@ step_mfma_kernel(StepArgs a) {
         for (int c = 1; c < 3; ++c)
             qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
         if (MULTI && L.write_half && a.half != nullptr) {
-            const unsigned KnF = (unsigned)a.KnF;
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
                 const int slot = a.ops.nodeface[2 * j + sl];
@@ -928,8 +916,8 @@ step_mfma_kernel(StepArgs a) {
                 const unsigned hid = (unsigned)k * nF + slot;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    stg(a.half + c * (size_t)KnF, hid,
-                        q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c])));
+                    bH.st(hid, c * HB,
+                          q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c])));
             }
         }
     }
@@ -1010,18 +998,10 @@ step_mfma_kernel(StepArgs a) {
                 out[c] = (float)val;
         }
     }
-    if constexpr (!MULTI) {
-        bQo.st(idx, 0, out[0]);
-        bQo.st(idx, FB, out[1]);
-        bQo.st(idx, 2u * FB, out[2]);
-        bQo.st(idx, 3u * FB, olo);
-    } else {
-        float* Qo = a.Q[1 - L.parity];
-        stg(Qo, idx, out[0]);
-        stg(Qo + KNp, idx, out[1]);
-        stg(Qo + 2 * (size_t)KNp, idx, out[2]);
-        stg(Qo + 3 * (size_t)KNp, idx, olo);
-    }
+    bQo.st(idx, 0, out[0]);
+    bQo.st(idx, FB, out[1]);
+    bQo.st(idx, 2u * FB, out[2]);
+    bQo.st(idx, 3u * FB, olo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1271,19 +1251,46 @@ static void dispatch(K kernel, int blocks, int threads, hipStream_t s, const Ste
 
 // matrix-core step kernel with W waves (EPW W elements) per block
 template <int N, int W>
-static void dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int EPW = 64 / mfma_lanes(N);
-    const int blocks = (n + EPW * W - 1) / (EPW * W);
+static int dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int EPW = 64 / mfma_lanes(N), EPB = EPW * W;
     const int bf = a.engine == ENGINE_MFMA_BF16X3 ? 1 : (a.engine == ENGINE_MFMA_BF16X6 ? 2 : 0);
     if (a.nlev > 1) {
-        if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, a, e0, e1);
-        else if (bf == 2) dispatch(step_mfma_kernel<N, true, W, 2>, blocks, 64 * W, s, a, e0, e1);
-        else dispatch(step_mfma_kernel<N, true, W, 0>, blocks, 64 * W, s, a, e0, e1);
+        // cut [k_begin, k_end) at the level boundaries into whole blocks
+        StepArgs m = a;
+        int blocks = 0;
+        m.parity_bits = 0;
+        m.active_bits = 0;
+        for (int l = 0; l < kMaxLevels; ++l) {
+            int lo = a.k_begin, hi = a.k_begin;
+            if (l < a.nlev) {
+                lo = a.lev[l].begin > a.k_begin ? a.lev[l].begin : a.k_begin;
+                hi = a.lev[l].end < a.k_end ? a.lev[l].end : a.k_end;
+                if (hi < lo) hi = lo;
+                m.parity_bits |= (unsigned)(a.lev[l].parity & 1) << l;
+                m.active_bits |= (unsigned)(a.lev[l].active & 1) << l;
+            }
+            m.seg_begin[l] = lo;
+            m.seg_end[l] = hi;
+            m.seg_block[l] = blocks;
+            blocks += (hi - lo + EPB - 1) / EPB;
+        }
+        m.seg_block[kMaxLevels] = blocks;
+        const long long qd = reinterpret_cast<const char*>(a.Q[1]) - reinterpret_cast<const char*>(a.Q[0]);
+        if (qd < 16 * a.KNp || qd + 16 * a.KNp >= (1ll << 32)) {
+            std::snprintf(g_dev_err, sizeof(g_dev_err), "state buffers out of one 32-bit view");
+            return -1;
+        }
+        m.q_pair_bytes = (unsigned)qd;
+        if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, m, e0, e1);
+        else if (bf == 2) dispatch(step_mfma_kernel<N, true, W, 2>, blocks, 64 * W, s, m, e0, e1);
+        else dispatch(step_mfma_kernel<N, true, W, 0>, blocks, 64 * W, s, m, e0, e1);
     } else {
+        const int blocks = (n + EPB - 1) / EPB;
         if (bf == 1) dispatch(step_mfma_kernel<N, false, W, 1>, blocks, 64 * W, s, a, e0, e1);
         else if (bf == 2) dispatch(step_mfma_kernel<N, false, W, 2>, blocks, 64 * W, s, a, e0, e1);
         else dispatch(step_mfma_kernel<N, false, W, 0>, blocks, 64 * W, s, a, e0, e1);
     }
+    return 0;
 }
 
 template <int N>
@@ -1295,9 +1302,9 @@ static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e
             constexpr int EPW = 64 / mfma_lanes(N);
             const int w = epb % EPW == 0 ? epb / EPW : 0;
             switch (w) {
-                case 1: dispatch_mfma<N, 1>(n, s, a, e0, e1); break;
-                case 2: dispatch_mfma<N, 2>(n, s, a, e0, e1); break;
-                case 4: dispatch_mfma<N, 4>(n, s, a, e0, e1); break;
+                case 1: if (dispatch_mfma<N, 1>(n, s, a, e0, e1)) return -1; break;
+                case 2: if (dispatch_mfma<N, 2>(n, s, a, e0, e1)) return -1; break;
+                case 4: if (dispatch_mfma<N, 4>(n, s, a, e0, e1)) return -1; break;
                 default:
                     std::snprintf(g_dev_err, sizeof(g_dev_err),
                                   "elements per block %d is not 1, 2 or 4 waves of %d elements", epb, EPW);

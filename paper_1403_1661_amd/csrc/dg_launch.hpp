@@ -87,6 +87,14 @@ struct StepArgs {
     const float* r_prev1;
     const float* r_prev2;
     float* half;           // [3][K*3Nfp] half-step face traces (multi-rate) or null
+    // multi-rate matrix-core kernel (filled by the launcher): the launch's
+    // element range cut at level boundaries, each level's part taking whole
+    // blocks so that a block belongs to one level
+    int seg_begin[kMaxLevels], seg_end[kMaxLevels];
+    int seg_block[kMaxLevels + 1];   // first block of each level's part; total last
+    unsigned parity_bits;  // bit l: parity of level l
+    unsigned active_bits;  // bit l: level l steps at this tick
+    unsigned q_pair_bytes; // byte distance from Q[0] to Q[1]
     const float* geo;      // [K][16]
     const int* conn;       // [K][4]
     double* means;         // [3][K]

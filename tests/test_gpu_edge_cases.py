@@ -104,3 +104,41 @@ def test_all_dry_domain(path):
     assert np.all((f & 3) == 2) and np.all((f >> 2) == 0)
     d = g.diagnostics(0)
     assert d["mass"] == 0.0 and d["pp_counts"][2] == wl.n_elements
+
+
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+def test_multirate_tiny_levels(path):
+    """Four MRAB levels of a few elements to a hundred (the coarsest smaller
+    than one block of the step kernels): every level's part of a launch is
+    ragged, and neighbours across level boundaries are read from the other
+    parity or from half-step traces (Section 4)."""
+    _require_gpu()
+    wl = W.c3(n0=1)
+    g = gpu_solver(wl, precision=path)
+    o = oracle_solver(wl)
+    lev, _ = g.levels(0)
+    assert np.array_equal(lev.astype(int), o.levels)
+    sizes = [int(np.sum(o.levels == l)) for l in range(1, wl.max_levels + 1)]
+    log(f"[mrab-tiny] {path} K={wl.n_elements} level sizes {sizes}")
+    g.advance(4)
+    o.run(4)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    log(f"[mrab-tiny] relL2 h={err['h']:.3e} m={err['m']:.3e}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert flag_flips(g.flags(0), o.flags) == (0, 0)
+
+
+def test_multirate_block_shapes_bitwise():
+    """The multi-rate launch cuts each level's element range into whole
+    blocks; 1, 2 or 4 waves per block change only that cut, so the MRAB
+    trajectories agree bit for bit."""
+    _require_gpu()
+    wl = W.c3(n0=2)
+    runs = []
+    for epb in (4, 8, 16):
+        g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
+        g.advance(5)
+        runs.append(g.get_state(0))
+    for other in runs[1:]:
+        for x, y in zip(other, runs[0]):
+            assert np.array_equal(x, y)
