@@ -578,6 +578,27 @@ __device__ __forceinline__ int face_node(int fn) {
     }
 }
 
+// lane exchange inside rows of 16 lanes by DPP moves (no LDS traffic); CTRL
+// is the DPP control: 0xB1 quad_perm [1,0,3,2] (lane i ^ 1), 0x4E quad_perm
+// [2,3,0,1] (lane i ^ 2), 0x141 row half mirror (lane 7 - i of the 8-lane
+// half), 0x140 row mirror (lane 15 - i)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// minimum over each row of 16 lanes, in every lane of the row (all lanes
+// of the wave active)
+__device__ __forceinline__ double row_min16(double x) {
+    x = fmin(x, dpp_f64<0xB1>(x));
+    x = fmin(x, dpp_f64<0x4E>(x));    // quad minimum
+    x = fmin(x, dpp_f64<0x141>(x));   // the other quad of the half row
+    return fmin(x, dpp_f64<0x140>(x));   // the other half row
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     // order this wave's LDS writes before its reads of other lanes' data
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -627,7 +648,9 @@ step_mfma_kernel(StepArgs a) {
         union {
             float A[EPW][3][RS];
             struct {
-                double Vd[EPW][3][LPE];   // updated h, hu, hv per node
+                double Vd[EPW][3][LPE + 1];   // updated h, hu, hv per node (rows padded
+                                              // so the reduction's column reads
+                                              // fall in distinct banks)
                 double Red[EPW][16];      // 1-3 means, 4-12 deviations
             } r;
         };
@@ -640,7 +663,7 @@ step_mfma_kernel(StepArgs a) {
     const int gbase = lane & ~(LPE - 1);   // first lane of the element
     const int el = wave * EPW + q;
     float (&sA)[EPW][3][RS] = lds[wave].A;
-    double (&sVd)[EPW][3][LPE] = lds[wave].r.Vd;
+    double (&sVd)[EPW][3][LPE + 1] = lds[wave].r.Vd;
     double (&sRed)[EPW][16] = lds[wave].r.Red;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     // multi-rate: the block's level (uniform) from the launcher's cut of the
@@ -739,8 +762,10 @@ step_mfma_kernel(StepArgs a) {
     const float lo0 = __shfl(lo, gbase);
     const float dlt = (eta - eta0) + (lo - lo0);
 
-    // ---- X^T rows: volume fluxes (negated), zero padding
-    if (node) {
+    // ---- X^T rows: volume fluxes (negated), zero padding.  Every lane
+    // computes (lanes that are not nodes hold a clamped node's finite data)
+    // and lanes that are not nodes store into the unread padding of the row.
+    {
         const float h = (eta - Bn) + lo;
         const float fv = 2.f * h * __builtin_amdgcn_rcpf(h * h + fmaxf(h * h, hvel * hvel));
         const float u = hu * fv, v = hv * fv;
@@ -748,10 +773,13 @@ step_mfma_kernel(StepArgs a) {
         const float F[3] = {hu, hu * u + p, hu * v};
         const float G[3] = {hv, hv * u, hv * v + p};
         const float rx = g0.x, ry = g0.y, sx = g0.z, sy = g0.w;
+        const int nm = -(int)node, pd = RL + (j & 3);   // branch-free selects
+        const int cr = pd ^ ((S::perm(j) ^ pd) & nm);
+        const int cs = pd ^ ((S::perm(Np + j) ^ pd) & nm);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sA[q][c][S::perm(j)] = -(rx * F[c] + ry * G[c]);
-            sA[q][c][S::perm(Np + j)] = -(sx * F[c] + sy * G[c]);
+            sA[q][c][cr] = -(rx * F[c] + ry * G[c]);
+            sA[q][c][cs] = -(sx * F[c] + sy * G[c]);
         }
     }
     // padding after the volume and after the lift columns (finite: the
@@ -927,9 +955,8 @@ step_mfma_kernel(StepArgs a) {
     sVd[q][0][j] = h64;
     sVd[q][1][j] = node ? (double)qn[1] : 0.0;
     sVd[q][2][j] = node ? (double)qn[2] : 0.0;
-    double hmin = node ? h64 : 1e300;
-#pragma unroll
-    for (int m = LPE / 2; m >= 1; m >>= 1) hmin = fmin(hmin, __shfl_xor(hmin, m, LPE));
+    double hmin = row_min16(node ? h64 : 1e300);
+    if constexpr (LPE == 32) hmin = fmin(hmin, __shfl_xor(hmin, 16));
     wave_lds_sync();
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
