@@ -656,6 +656,14 @@ step_mfma_kernel(StepArgs a) {
         };
     };
     __shared__ __attribute__((aligned(16))) WaveLds lds[WPB];
+    // FP32 operator table of the block: lane l of tile t reads its KS steps
+    // as float4 chunks from row t * 64 + l (row stride padded so that the
+    // 128-bit reads of consecutive lanes fall in distinct banks)
+    // (blocks of four waves; smaller blocks read the table from global
+    // memory, so the launch-shape search covers both ways)
+    constexpr bool OPL = !BF && WPB == 4;
+    constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
+    __shared__ __attribute__((aligned(16))) float sOp[OPL ? S::NT * 64 * OPS : 4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -758,6 +766,15 @@ step_mfma_kernel(StepArgs a) {
         }
     }
 
+    if constexpr (OPL) {
+        // stage the operator table: global order (t, s, lane) to LDS rows
+        for (int e = tid; e < NT * KS * 64; e += 64 * WPB) {
+            const int t = e / (KS * 64), r = e - t * (KS * 64);
+            sOp[(t * 64 + (r & 63)) * OPS + (r >> 6)] = ldg(a.ops.Amfma, (unsigned)e);
+        }
+        __syncthreads();
+    }
+
     const float eta0 = __shfl(eta, gbase);
     const float lo0 = __shfl(lo, gbase);
     const float dlt = (eta - eta0) + (lo - lo0);
@@ -816,11 +833,22 @@ step_mfma_kernel(StepArgs a) {
             av[4 * s4] = v4.x; av[4 * s4 + 1] = v4.y; av[4 * s4 + 2] = v4.z; av[4 * s4 + 3] = v4.w;
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t) {
+            float ov[4 * SV4];
 #pragma unroll
-            for (int s = 0; s < SV; ++s)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    av[s], ldg(a.ops.Amfma, (unsigned)((t * KS + s) * 64 + lane)), acc[t], 0, 0, 0);
+            for (int s4 = 0; s4 < SV4; ++s4) {
+                if constexpr (OPL) {
+                    const float4 o4 = *reinterpret_cast<const float4*>(&sOp[(t * 64 + lane) * OPS + 4 * s4]);
+                    ov[4 * s4] = o4.x; ov[4 * s4 + 1] = o4.y; ov[4 * s4 + 2] = o4.z; ov[4 * s4 + 3] = o4.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (4 * s4 + i < KS) ov[4 * s4 + i] = ldg(a.ops.Amfma, (unsigned)((t * KS + 4 * s4 + i) * 64 + lane));
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SV; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], ov[s], acc[t], 0, 0, 0);
+        }
     } else {
         // X and the operator split into P = BF + 1 BF16 parts; the operator
         // table holds hi, mid, lo parts (the two-part split uses hi, mid)
@@ -893,11 +921,25 @@ step_mfma_kernel(StepArgs a) {
             af[4 * (s4 - F0) + 2] = v4.z; af[4 * (s4 - F0) + 3] = v4.w;
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t) {
+            float ov[4 * (F1 - F0)];
+#pragma unroll
+            for (int s4 = F0; s4 < F1; ++s4) {
+                if constexpr (OPL) {
+                    const float4 o4 = *reinterpret_cast<const float4*>(&sOp[(t * 64 + lane) * OPS + 4 * s4]);
+                    ov[4 * (s4 - F0)] = o4.x; ov[4 * (s4 - F0) + 1] = o4.y;
+                    ov[4 * (s4 - F0) + 2] = o4.z; ov[4 * (s4 - F0) + 3] = o4.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (4 * s4 + i >= SV && 4 * s4 + i < KS)
+                            ov[4 * (s4 - F0) + i] = ldg(a.ops.Amfma, (unsigned)((t * KS + 4 * s4 + i) * 64 + lane));
+                }
+            }
 #pragma unroll
             for (int s = SV; s < KS; ++s)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    af[s - 4 * F0], ldg(a.ops.Amfma, (unsigned)((t * KS + s) * 64 + lane)), acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s - 4 * F0], ov[s - 4 * F0], acc[t], 0, 0, 0);
+        }
     } else {
         constexpr int P = BF + 1;
         const bf16x8* tab = reinterpret_cast<const bf16x8*>(a.ops.Abf);
