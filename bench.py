@@ -67,6 +67,26 @@ def copy_reference(n_bytes: int = 1 << 29, reps: int = 5):
                       "reps": reps}), flush=True)
 
 
+def copy_ceiling(torch, n_bytes: int = 1 << 29, reps: int = 20) -> float:
+    """Measured stream-copy bandwidth of this GPU in GB/s (bytes read plus
+    bytes written per second): a device-to-device copy of 512 MiB, twice the
+    size of the last-level cache, timed with events after a warm-up."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    del src, dst
+    return 2.0 * n_bytes * reps / sec / 1e9
+
+
 def step_kernel_bytes(Np: int) -> int:
     """Algorithmic HBM bytes per element of one single-rate step (what the
     method has to move, each array once, FP32 nodal data): state h, hu, hv
@@ -218,6 +238,7 @@ def main():
     bytes_launch = step_kernel_bytes(Np) * elems
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
     del s
+    copy_gbps = copy_ceiling(torch)
 
     plain = None
     if not args.no_plain and args.precision != "plain_fp32":
@@ -251,6 +272,7 @@ def main():
         "hbm_gbps_algorithmic_step": step_kernel_bytes(Np) * (per_step / Np) * steps / t / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "copy_ceiling_gbps": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps,
                      "kernel": f"{kname}<{wl.N}> (fused RHS + AB3 + positivity)",
                      "kernel_avg_us": avg_us, "launches_timed": launches,
                      "elements_per_launch": elems, "bytes_per_launch": bytes_launch},

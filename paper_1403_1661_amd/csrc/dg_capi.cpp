@@ -36,7 +36,7 @@ int fail(int code, const std::string& msg) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t Q[2], R[3], half, means, devs, flags, counters;   // dynamic (checkpointed)
+    size_t Q[2], R[3], half, mrec, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
     size_t B, dB, geo, conn, stencil;
     size_t Dr, Ds, LIFT, Amfma, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
@@ -131,8 +131,8 @@ static void compute_layout(dg_solver* h) {
     l.Q[1] = take(4 * KNp * 4);
     for (int s = 0; s < 3; ++s) l.R[s] = take(3 * KNp * 4);
     l.half = take(h->L > 1 ? 3 * KnF * 4 : 0);
-    l.means = take(3 * size_t(h->K) * 8);
-    l.devs = take(9 * size_t(h->K) * 8);
+    l.mrec = take(4 * size_t(h->K) * 8);
+    l.devs = take(9 * size_t(h->K) * 4);
     l.flags = take(size_t(h->K));
     l.counters = take(64);
     l.dyn_end = o;
@@ -646,8 +646,8 @@ static StepArgs base_step_args(dg_solver* h) {
     a.half = h->L > 1 ? reinterpret_cast<float*>(h->ws + l.half) : nullptr;
     a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
     a.conn = reinterpret_cast<const int*>(h->ws + l.conn);
-    a.means = reinterpret_cast<double*>(h->ws + l.means);
-    a.devs = reinterpret_cast<double*>(h->ws + l.devs);
+    a.mrec = reinterpret_cast<double*>(h->ws + l.mrec);
+    a.devs = reinterpret_cast<float*>(h->ws + l.devs);
     a.flags = reinterpret_cast<uint8_t*>(h->ws + l.flags);
     a.counters = reinterpret_cast<unsigned long long*>(h->ws + l.counters);
     a.ops.Dr = reinterpret_cast<const float*>(h->ws + l.Dr);
@@ -704,7 +704,7 @@ static TvbArgs tvb_args(dg_solver* h, const StepArgs& sa) {
     t.geo = sa.geo;
     t.conn = sa.conn;
     t.stencil = reinterpret_cast<const float*>(h->ws + h->lay.stencil);
-    t.means = sa.means;
+    t.mrec = sa.mrec;
     t.devs = sa.devs;
     t.flags = sa.flags;
     t.phi = sa.ops.phi;

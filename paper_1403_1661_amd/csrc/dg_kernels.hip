@@ -22,10 +22,12 @@
 //   5. Adams-Bashforth update with the level's weights (Algorithm 4.1), RHS
 //      written to the ring, half-step face traces for finer neighbours;
 //   6. per-element FP64 reductions (min depth, means, P1 edge-midpoint
-//      deviations) and the positivity limiter of Algorithm 5.2.
-// TVB kernel (one lane per element, FP64): characteristic minmod on the
-// edge-midpoint deviations against the neighbours' means, balancing, and the
-// depth rescaling of Eq. 5.3 (Section 5.3).
+//      deviations) and the positivity limiter of Algorithm 5.2; the element
+//      leaves a record of its FP64 means and positivity code, and its
+//      deviations (stored in FP32) unless it is dry.
+// TVB kernel (four lanes per element, FP64 arithmetic): characteristic minmod
+// on the edge-midpoint deviations against the neighbours' means, balancing,
+// and the depth rescaling of Eq. 5.3 (Section 5.3).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -430,10 +432,13 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.means[c * (long long)a.K + k] = mean[c];
+        for (int c = 0; c < 3; ++c) a.mrec[4 * (long long)k + c] = mean[c];
+        a.mrec[4 * (long long)k + 3] = (double)code;
+        if (code != 2) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) a.devs[q * (long long)a.K + k] = scale * sRed[e][4 + q];
-        a.flags[k] = (uint8_t)(code | (code != 2 ? kTvbCandidate : 0));
+            for (int q = 0; q < 9; ++q) a.devs[q * (long long)a.K + k] = (float)(scale * sRed[e][4 + q]);
+        }
+        a.flags[k] = (uint8_t)code;
         sRed[e][13] = (double)code;
         sRed[e][14] = scale;
         sRed[e][15] = hdry;
@@ -1039,14 +1044,16 @@ step_mfma_kernel(StepArgs a) {
     const double mean0 = code == 2 ? hdry : hb;
     const double mean1 = code == 2 ? 0.0 : sRed[q][2];
     const double mean2 = code == 2 ? 0.0 : sRed[q][3];
-    // ---- hand-off to the TVB kernel: post-limiter means of every element,
-    // P1 midpoint deviations of every element that is not dry
-    if (live && j < 3) stg(a.means, (unsigned)j * (unsigned)a.K + k, j == 0 ? mean0 : (j == 1 ? mean1 : mean2));
+    // ---- hand-off to the TVB kernel: a 32-byte record of post-limiter means
+    // and positivity code for every element, P1 midpoint deviations (FP32)
+    // of every element that is not dry
+    if (live && j < 4)
+        stg(a.mrec, 4u * (unsigned)k + j, j == 0 ? mean0 : (j == 1 ? mean1 : (j == 2 ? mean2 : (double)code)));
     if (live && j < 9 && code != 2) {
         const int ed = j / 3, r = j % 3;   // field r at edge ed
-        stg(a.devs, (unsigned)(3 * r + ed) * (unsigned)a.K + k, scale * sRed[q][4 + 3 * r + ed]);
+        stg(a.devs, (unsigned)(3 * r + ed) * (unsigned)a.K + k, (float)(scale * sRed[q][4 + 3 * r + ed]));
     }
-    if (live && j == 0) a.flags[k] = (uint8_t)(code | (code != 2 ? kTvbCandidate : 0));
+    if (live && j == 0) a.flags[k] = (uint8_t)code;
     if (!node) return;
     // ---- limited nodal values and the new state
     float out[3] = {qn[0], qn[1], qn[2]};
@@ -1078,8 +1085,9 @@ step_mfma_kernel(StepArgs a) {
 // FP64.  Four lanes per element: lane t < 3 owns edge t (its neighbour t,
 // its stencil row, its characteristic decomposition); the balancing and the
 // P1 output are shared by the quad (lane t writes nodes t, t+4, ...).
-// Neighbour flags are read while neighbours rewrite theirs, which is safe:
-// a rewrite keeps the positivity bits (0-1), the only bits read here.
+// Means and positivity codes come from the step kernel's per-element records,
+// which this kernel only reads, so the order in which elements are limited
+// does not matter.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const int tid = threadIdx.x;
@@ -1089,47 +1097,37 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     if (k >= a.k_end) return;   // the whole quad leaves together
     const unsigned K = (unsigned)a.K;
     const int ed = t < 3 ? t : 0;   // lane 3 shadows edge 0 and is ignored
-    // round 1: everything indexed by k alone
-    const uint8_t fl = a.flags[k];
+    // round 1: everything indexed by k alone; the element's record holds its
+    // post-positivity means and positivity code (the step kernel's snapshot)
+    const double2* rec = reinterpret_cast<const double2*>(a.mrec);
+    const double2 r01 = ldg(rec, 2u * k), r23 = ldg(rec, 2u * k + 1u);
     const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)k);
-    const uint8_t pp = fl & 3;
+    const uint8_t pp = (uint8_t)r23.y;
     if (pp == 2) {
         if (t == 0) a.flags[k] = pp;
         return;
     }
-    const bool cand = (fl & kTvbCandidate) != 0;
-    double qb[3] = {0.0, 0.0, 0.0};
-    double dev[3] = {0.0, 0.0, 0.0};   // field c at edge ed
-    float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-    float M2 = 0.f;
-    int pairs = 0;
-    if (cand) {
+    const double qb[3] = {r01.x, r01.y, r23.x};
+    double dev[3];   // field c at edge ed
 #pragma unroll
-        for (int c = 0; c < 3; ++c) qb[c] = ldg(a.means, c * K + k);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dev[c] = ldg(a.devs, (3 * c + ed) * K + k);
-        st = ldg(reinterpret_cast<const float4*>(a.stencil), 4u * k + ed);   // alpha_j, alpha_k, ex, ey
-        const float2 mp = ldg(reinterpret_cast<const float2*>(a.stencil), 8u * k + 6u);
-        M2 = mp.x;
-        pairs = __float_as_int(mp.y);
-    }
-    // round 2: neighbour t (flag, and means for candidates)
+    for (int c = 0; c < 3; ++c) dev[c] = (double)ldg(a.devs, (3 * c + ed) * K + k);
+    const float4 st = ldg(reinterpret_cast<const float4*>(a.stencil), 4u * k + ed);   // alpha_j, alpha_k, ex, ey
+    const float2 mp = ldg(reinterpret_cast<const float2*>(a.stencil), 8u * k + 6u);
+    const float M2 = mp.x;
+    const int pairs = __float_as_int(mp.y);
+    // round 2: neighbour t's record (means, and its code for the dry test)
     const int nbt = t == 0 ? cn.x : (t == 1 ? cn.y : (t == 2 ? cn.z : -1));
     bool dry_t = false;
     double nm[3] = {0.0, 0.0, 0.0};
     if (nbt >= 0) {
-        dry_t = (a.flags[nbt] & 3) == 2;
-        if (cand) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) nm[c] = ldg(a.means, c * K + (unsigned)nbt);
-        }
+        const double2 n01 = ldg(rec, 2u * (unsigned)nbt), n23 = ldg(rec, 2u * (unsigned)nbt + 1u);
+        dry_t = n23.y == 2.0;
+        nm[0] = n01.x;
+        nm[1] = n01.y;
+        nm[2] = n23.x;
     }
     if (((__ballot(dry_t) >> qb4) & 0xFull) != 0) {   // a face neighbour is dry: skipped
         if (t == 0) a.flags[k] = pp;
-        return;
-    }
-    if (!cand) {   // every characteristic increment within M d^2
-        if (t == 0) a.flags[k] = pp | (1 << 2);
         return;
     }
     // mean difference across face t (a wall mirrors the momentum mean)

@@ -8,10 +8,6 @@
 namespace dgswe {
 
 constexpr int kMaxLevels = 6;
-// flag bit set by the step kernels: the element goes through the TVB
-// limiter (it is not dry; its FP64 midpoint deviations were written)
-constexpr int kTvbCandidate = 16;
-
 // Face node fn = f (N+1) + p of the reference triangle (faces s = -1, r + s
 // = 0, r = -1, each in counter-clockwise order) for nodes numbered row by row
 // in s, row j holding N+1-j nodes in increasing r.  The host checks its face
@@ -97,8 +93,8 @@ struct StepArgs {
     unsigned q_pair_bytes; // byte distance from Q[0] to Q[1]
     const float* geo;      // [K][16]
     const int* conn;       // [K][4]
-    double* means;         // [3][K]
-    double* devs;          // [9][K] P1 edge-midpoint deviations (TVB candidates)
+    double* mrec;          // [K][4] post-positivity means h, hu, hv and the positivity code
+    float* devs;           // [9][K] P1 edge-midpoint deviations (elements that are not dry)
     uint8_t* flags;        // [K]
     unsigned long long* counters;  // [0] negative-mean events
     DevOps ops;
@@ -118,8 +114,8 @@ struct TvbArgs {
     const float* geo;
     const int* conn;
     const float* stencil;  // [K][16]
-    const double* means;
-    const double* devs;
+    const double* mrec;    // [K][4] as written by the step kernel
+    const float* devs;     // [9][K]
     uint8_t* flags;
     const double* phi;     // 3 x Np
     double g, h0, nu;
