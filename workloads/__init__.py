@@ -343,6 +343,110 @@ def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Wor
                     cfl=0.2, seed=seed, notes="small beach")
 
 
+# ---------------------------------------------------------------------------
+# Closed-form wet/dry cases of the paper's numerical section.  Each workload
+# carries ``extra["exact"](x, y, t) -> (h, hu, hv)`` (the printed solution),
+# ``extra["t0"]`` (the time of the initial state), ``extra["t_end"]`` and
+# ``extra["hvel"]``, the depth below which velocities are desingularised
+# (the paper says nothing about velocities in thin films; the two curved-bed
+# cases need it at a few per cent of their depth scale, see each case).
+
+
+def parabolic_bowl(n: int = 16, N: int = 2, t_end_periods: float = 0.25) -> Workload:
+    """Thacker's periodic flow in a paraboloid bed (Section 6, parabolic
+    bowl): B = alpha r^2 on the 8000 m square centred at the origin, alpha =
+    1.6e-7, X = 1, Y = -0.41884, omega^2 = 8 g alpha; h is the printed
+    quadratic in r inside the moving shoreline and zero outside, u and v are
+    linear in x and y.  The water never reaches the walls."""
+    alpha, X, Y = 1.6e-7, 1.0, -0.41884
+    g = G_DEFAULT
+    om = math.sqrt(8.0 * g * alpha)
+    vx, vy, etov = structured_mesh(n, n, -4000.0, 4000.0, -4000.0, 4000.0)
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return on_bed_grid(alpha * (x * x + y * y))
+
+    def exact(x, y, t):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        den = X + Y * math.cos(om * t)
+        r2 = x * x + y * y
+        h = np.maximum(0.0, 1.0 / den + alpha * (Y * Y - X * X) * r2 / (den * den))
+        f = -Y * om * math.sin(om * t) / den * 0.5
+        return h, h * f * x, h * f * y
+
+    period = 2.0 * math.pi / om
+    return Workload("bowl", N, [Instance(vx, vy, etov, bath, lambda x, y: exact(x, y, 0.0), "bowl")],
+                    steps=0, cfl=0.2, g=g, notes=f"parabolic bowl {n}x{n}x2, N={N}",
+                    extra={"exact": exact, "t0": 0.0, "t_end": t_end_periods * period, "period": period,
+                           "local_radius": 500.0, "hvel": 0.1})
+
+
+def rarefaction(nx: int = 20, N: int = 2, t_end: float = 10.0, cfl: float = 0.1,
+                width: float = 2.5) -> Workload:
+    """Dam-break rarefaction into a dry bed on a flat bottom (Section 6,
+    rarefaction wave): g = 1, h0 = 1, xi = (x - 20)/t; still water h0 for
+    xi < -sqrt(g h0), dry for xi > 2 sqrt(g h0), and h = (xi - 2 sqrt(g
+    h0))^2 / (9 g), u = 2/3 (xi + sqrt(g h0)) between.  The flow is
+    independent of y, so a strip of the given width (cells as close to
+    square as its width allows) stands for the 50 x 40 domain; the state at
+    t = 2 is the initial condition and the TVB limiter is off, as in the
+    paper."""
+    g, h0 = 1.0, 1.0
+    Lx = 50.0
+    ny = max(1, int(round(nx * width / Lx)))
+    vx, vy, etov = structured_mesh(nx, ny, 0.0, Lx, 0.0, width)
+    c0 = math.sqrt(g * h0)
+
+    def bath(x, y):
+        return _zeros_like(np.asarray(x, dtype=np.float64))
+
+    def exact(x, y, t):
+        x = np.asarray(x, dtype=np.float64)
+        xi = (x - 20.0) / t
+        h = np.where(xi < -c0, h0, np.where(xi > 2.0 * c0, 0.0, (xi - 2.0 * c0) ** 2 / (9.0 * g)))
+        u = np.where((xi >= -c0) & (xi <= 2.0 * c0), 2.0 / 3.0 * (xi + c0), 0.0)
+        return h, h * u, _zeros_like(x)
+
+    return Workload("rarefaction", N, [Instance(vx, vy, etov, bath, lambda x, y: exact(x, y, 2.0), "rare")],
+                    steps=0, cfl=cfl, g=g, notes=f"rarefaction strip {nx}x{ny}x2, N={N}",
+                    extra={"exact": exact, "t0": 2.0, "t_end": t_end, "local_x": (15.0, 35.0), "tvb": False,
+                           "width": width, "hvel": 1e-3})
+
+
+def oscillating_lake(n: int = 16, N: int = 2, t_end_periods: float = 1.0) -> Workload:
+    """Planar free surface rotating in a paraboloid bed (Section 6,
+    oscillating lake): [-2,2]^2, B = h0 (x^2 + y^2) / a^2 with a = 1,
+    h0 = 0.1, sigma = 0.5, omega = sqrt(2 g h0) / a; h = max(0, sigma h0 /
+    a^2 (2x cos wt + 2y sin wt - sigma) + h0 - B), u = -sigma w sin wt,
+    v = sigma w cos wt; reflecting walls, both limiters on."""
+    a, h0, sg = 1.0, 0.1, 0.5
+    g = G_DEFAULT
+    om = math.sqrt(2.0 * g * h0) / a
+    vx, vy, etov = structured_mesh(n, n, -2.0, 2.0, -2.0, 2.0)
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return on_bed_grid(h0 * (x * x + y * y) / (a * a))
+
+    def exact(x, y, t):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        b = h0 * (x * x + y * y) / (a * a)
+        h = np.maximum(0.0, sg * h0 / (a * a) * (2.0 * x * math.cos(om * t) + 2.0 * y * math.sin(om * t) - sg)
+                       + h0 - b)
+        return h, h * (-sg * om * math.sin(om * t)), h * (sg * om * math.cos(om * t))
+
+    period = 2.0 * math.pi / om
+    return Workload("lake", N, [Instance(vx, vy, etov, bath, lambda x, y: exact(x, y, 0.0), "lake")],
+                    steps=0, cfl=0.2, g=g, notes=f"oscillating lake {n}x{n}x2, N={N}",
+                    extra={"exact": exact, "t0": 0.0, "t_end": t_end_periods * period, "period": period,
+                           "hvel": 1e-2})
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
 
 
