@@ -206,7 +206,7 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         const bool ok = mfma ? (e == epw || e == 2 * epw || e == 4 * epw) : e == valu_e;
         if (!ok)
             return fail(DG_EINVAL, mfma ? "elems_per_block must be 0 or 1, 2, 4 waves of 64/lanes elements on "
-                                          "the MFMA paths (N <= 4: 4, 8, 16; N = 5: 2, 4, 8)"
+                                          "the MFMA paths (N = 1, 2, 4: 4, 8, 16; N = 3: 5, 10, 20; N = 5: 3, 6, 12)"
                                         : "elems_per_block must be 0 or floor(256 / Np) on the VALU paths");
     }
     std::unique_ptr<dg_solver> h;
@@ -439,7 +439,7 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     // FP32 MFMA B operand: column tile t (nodes 16 t .. 16 t + 15), step st,
     // lane ln -> Op[16 t + ln % 16][4 st + ln / 16]
     std::vector<float> amfma;
-    const int NT = mfma_lanes(h->p.N) / 16;
+    const int NT = mfma_tiles(h->p.N);
     if (h->p.N <= 5) {
         const int KV = mfma_kv(h->p.N), KS = mfma_steps(h->p.N);
         amfma.assign(size_t(NT) * KS * 64, 0.f);

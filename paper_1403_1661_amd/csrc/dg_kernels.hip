@@ -521,7 +521,8 @@ struct MShape {
     static constexpr int nF = 3 * (N + 1);
     static constexpr int LPE = mfma_lanes(N);                         // lanes per element
     static constexpr int EPW = 64 / LPE;                              // elements per wave
-    static constexpr int NT = LPE / 16;                               // 16-node column tiles
+    static constexpr int NT = mfma_tiles(N);                          // 16-node column tiles
+    static constexpr bool CMP = mfma_compact(N);                      // packed lane groups
     static constexpr int KQ = BF ? 32 : 4;                            // K per MFMA step
     static constexpr int KV = mfma_kv(N);                             // first LIFT column
     static constexpr int KS = BF ? (KV + nF + 31) / 32 : mfma_steps(N);
@@ -531,6 +532,22 @@ struct MShape {
     static constexpr int RS = RL + 4;                                 // LDS row stride (floats)
     static constexpr int KR = (Np + 3) / 4;                           // FP64 reduction steps
     static_assert(Np <= LPE && nF <= LPE, "element must fit its lane group");
+    static_assert(CMP ? 3 * EPW <= 16 : (LPE == 16 && NT == 1), "one 16-row tile of element x field rows");
+    static constexpr int OR = 20;   // row stride (floats) of the packed layout's result transpose
+    // packed groups: element r / 3 and field r % 3 of row r < 3 EPW from
+    // 4-bit and 2-bit tables (rows past 3 EPW map to element 0, field 0)
+    static constexpr unsigned long long row_element_bits() {
+        unsigned long long b = 0;
+        for (int r = 0; r < 16; ++r) b |= (unsigned long long)(r < 3 * EPW ? r / 3 : 0) << (4 * r);
+        return b;
+    }
+    static constexpr unsigned row_field_bits() {
+        unsigned b = 0;
+        for (int r = 0; r < 16; ++r) b |= (unsigned)(r < 3 * EPW ? r % 3 : 0) << (2 * r);
+        return b;
+    }
+    static __device__ __forceinline__ int row_element(int r) { return (int)((row_element_bits() >> (4 * r)) & 15ull); }
+    static __device__ __forceinline__ int row_field(int r) { return (int)((row_field_bits() >> (2 * r)) & 3u); }
     static __device__ __forceinline__ int perm(int k) {
         if constexpr (BF) return ((k >> 3) & 3) * (8 * KS) + (k >> 5) * 8 + (k & 7);
         else return (k & 3) * KSP + (k >> 2);
@@ -640,8 +657,15 @@ struct BufF32 {
     }
 };
 
+// occupancy target (waves per SIMD) of the matrix-core kernel: what its
+// register use allows without spills (the BF16 splits and the multi-rate
+// bookkeeping hold more live values; N = 5 holds two accumulator tiles)
+constexpr int mfma_waves_target(int N, bool multi, int bf) {
+    return (bf == 2 ? (multi ? 4 : 5) : (bf ? (multi ? 5 : 6) : (multi ? 6 : 7))) - (N == 5 ? 1 : 0);
+}
+
 template <int N, bool MULTI, int WPB, int BF>
-__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(BF == 2 ? (MULTI ? 4 : 5) : (BF ? (MULTI ? 5 : 6) : (MULTI ? 6 : 7)), 8)))
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(mfma_waves_target(N, MULTI, BF), 8)))
 step_mfma_kernel(StepArgs a) {
     using S = MShape<N, BF>;
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, KV = S::KV, KS = S::KS, SV = S::SV;
@@ -652,6 +676,7 @@ step_mfma_kernel(StepArgs a) {
     struct WaveLds {
         union {
             float A[EPW][3][RS];
+            float O[NT * 16][S::OR];   // packed layout: contraction result, node-major
             struct {
                 double Vd[EPW][3][LPE + 1];   // updated h, hu, hv per node (rows padded
                                               // so the reduction's column reads
@@ -672,8 +697,13 @@ step_mfma_kernel(StepArgs a) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int q = lane / LPE, j = lane % LPE;
-    const int gbase = lane & ~(LPE - 1);   // first lane of the element
+    // packed layout: lanes past EPW * LPE are spare; they shadow the wave's
+    // last element with the group index LPE (a padding slot everywhere) and
+    // are never live
+    const bool spare = S::CMP && lane >= EPW * LPE;
+    const int q = spare ? EPW - 1 : lane / LPE;
+    const int j = spare ? LPE : lane - q * LPE;
+    const int gbase = q * LPE;   // first lane of the element
     const int el = wave * EPW + q;
     float (&sA)[EPW][3][RS] = lds[wave].A;
     double (&sVd)[EPW][3][LPE + 1] = lds[wave].r.Vd;
@@ -689,7 +719,7 @@ step_mfma_kernel(StepArgs a) {
     const LevelArgs L = a.lev[lv];
     const int sbeg = MULTI ? a.seg_begin[lv] : a.k_begin, send = MULTI ? a.seg_end[lv] : a.k_end;
     const int k = sbeg + (blk - (MULTI ? a.seg_block[lv] : 0)) * (EPW * WPB) + el;
-    const bool live = k < send;
+    const bool live = !spare && k < send;
     const bool node = live && j < Np;
     // loads are unconditional: lanes past the last element of the block's
     // range read that element and lanes j >= Np read node Np - 1; their
@@ -806,25 +836,29 @@ step_mfma_kernel(StepArgs a) {
     }
     // padding after the volume and after the lift columns (finite: the
     // operator is zero there)
-    for (int t = j; t < KV - 2 * Np; t += LPE) {
+    if constexpr (KV - 2 * Np > 0) {
+        for (int t = j; t < KV - 2 * Np; t += LPE) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + t)] = 0.f;
+            for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + t)] = 0.f;
+        }
     }
-    for (int t = j; t < RL - (KV + nF); t += LPE) {
+    if constexpr (RL - (KV + nF) > 0) {
+        for (int t = j; t < RL - (KV + nF); t += LPE) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + t)] = 0.f;
+            for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + t)] = 0.f;
+        }
     }
     wave_lds_sync();
 
     // ---- volume part of the contraction on the matrix cores, issued before
     // the face flux so that it overlaps the neighbour loads
-    // A-operand row r = lane % 16 holds field r % 4 of element r / (4 NT) of
-    // this wave: with two column tiles every element's rows appear twice, so
-    // that tile t lands in the lanes of nodes 16 t .. 16 t + 15.  Field row 3
-    // is not contracted (its lanes read field 0, results unused).
+    // A-operand row r = lane % 16: 16-lane groups: field r % 4 of element
+    // r / 4 (field row 3 reads field 0, its results unused), so the result
+    // of node j lands in the lane of node j; packed groups: field r % 3 of
+    // element r / 3 (rows past 3 EPW read element 0, unused).
     const int ar = lane & 15;
-    const int ae = (ar >> 2) / NT;
-    const int arow = (ar & 3) == 3 ? 0 : (ar & 3);
+    const int ae = S::CMP ? S::row_element(ar) : (ar >> 2);
+    const int arow = S::CMP ? S::row_field(ar) : ((ar & 3) == 3 ? 0 : (ar & 3));
     const int ag = lane >> 4;           // K group supplied by this lane
     floatx4 acc[NT];
 #pragma unroll
@@ -962,13 +996,27 @@ step_mfma_kernel(StepArgs a) {
             }
         }
     }
-    // lane with node j takes column tile j / 16 (row group: its element, copy j / 16)
-    floatx4 accj = acc[0];
-    if constexpr (NT == 2) accj = j < 16 ? acc[0] : acc[1];
     float Rn[3];
-    Rn[0] = accj[0];
-    Rn[1] = accj[1] - g * dlt * dBx;
-    Rn[2] = accj[2] - g * dlt * dBy;
+    if constexpr (!S::CMP) {   // the lane of node j holds rows 4 q .. 4 q + 2 of column j
+        Rn[0] = acc[0][0];
+        Rn[1] = acc[0][1];
+        Rn[2] = acc[0][2];
+    } else {
+        // packed groups: D[row][node] to LDS node-major (lane c + 16 g of tile
+        // t holds rows 4 g .. 4 g + 3 of node column 16 t + c), then each lane
+        // reads rows 3 q .. 3 q + 2 of its node
+        float (&sO)[NT * 16][S::OR] = lds[wave].O;
+        wave_lds_sync();   // X^T reads done before the results overwrite them
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            *reinterpret_cast<float4*>(&sO[16 * t + (lane & 15)][4 * (lane >> 4)]) =
+                make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Rn[c] = sO[j][3 * q + c];
+    }
+    Rn[1] -= g * dlt * dBx;
+    Rn[2] -= g * dlt * dBy;
 
     // ---- Adams-Bashforth update, RHS ring, half-step traces
     float qn[3] = {eta, hu, hv};
@@ -998,21 +1046,34 @@ step_mfma_kernel(StepArgs a) {
     }
     // ---- FP64 element reductions on the matrix cores, min depth by shuffles
     const double h64 = node ? (double)qn[0] - (double)Bn + (double)qlo : 0.0;
-    wave_lds_sync();   // X^T reads done before the node values overwrite them
+    wave_lds_sync();   // X^T / result reads done before the node values overwrite them
     sVd[q][0][j] = h64;
     sVd[q][1][j] = node ? (double)qn[1] : 0.0;
     sVd[q][2][j] = node ? (double)qn[2] : 0.0;
-    double hmin = row_min16(node ? h64 : 1e300);
-    if constexpr (LPE == 32) hmin = fmin(hmin, __shfl_xor(hmin, 16));
+    double hmin = node ? h64 : 1e300;
+    if constexpr (!S::CMP) {
+        hmin = row_min16(hmin);   // the element is one 16-lane DPP row
+    } else {
+        // rotation doubling inside the group: after the shift s every lane
+        // holds the minimum of 2 s consecutive (cyclic) lanes of its group
+#pragma unroll
+        for (int sh = 1; sh < LPE; sh <<= 1) {
+            const int pj = j + sh;   // j <= LPE and sh < LPE: one wrap at most
+            hmin = fmin(hmin, __shfl(hmin, gbase + (pj >= LPE ? pj - LPE : pj)));
+        }
+    }
     wave_lds_sync();
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
-        const int c = lane & 15;          // column: element c/4, field c%4
-        const int ec = c >> 2, fc = c & 3;
-        const bool col = fc < 3 && ec < EPW;
+        // column c: element c / 4, field c % 4 (16-lane groups) or element
+        // c / 3, field c % 3 (packed groups); node rows past Np read nothing
+        const int c = lane & 15;
+        const int ec = S::CMP ? S::row_element(c) : c >> 2, fc = S::CMP ? S::row_field(c) : c & 3;
+        const bool col = S::CMP ? c < 3 * EPW : (fc < 3 && ec < EPW);
 #pragma unroll
         for (int s = 0; s < S::KR; ++s) {
-            const double bv = col ? sVd[ec < EPW ? ec : 0][fc < 3 ? fc : 0][4 * s + ag] : 0.0;
+            const int nd = 4 * s + ag;
+            const double bv = (col && nd < Np) ? sVd[ec < EPW ? ec : 0][fc < 3 ? fc : 0][nd < Np ? nd : 0] : 0.0;
             red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red,
                                                        0, 0, 0);
         }

@@ -143,14 +143,22 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
 int launch_tvb(const TvbArgs& a, void* stream);
 int launch_diag(const DiagArgs& a, void* stream);
 // elements per block: matrix-core kernel 1, 2 or 4 waves of 64 / lanes
-// elements (N <= 4: 4, 8, 16; N = 5: 2, 4, 8), default 4 waves; VALU kernel
-// floor(256 / Np) (fixed)
+// elements (N = 1, 2, 4: 4, 8, 16; N = 3: 5, 10, 20; N = 5: 3, 6, 12),
+// default 4 waves; VALU kernel floor(256 / Np) (fixed)
 constexpr int kMfmaDefaultWaves = 4;
 int step_elems_per_block(int N, int engine);
 
-// Lanes per element of the matrix-core kernel: 16 (Np <= 16, four elements
-// per wave) or 32 (N = 5, two elements per wave, two 16-node column tiles)
-constexpr int mfma_lanes(int N) { return (N + 1) * (N + 2) / 2 <= 16 ? 16 : 32; }
+// Lane groups of the matrix-core kernel.  N = 1, 2, 4: 16 lanes per element
+// (four elements per wave), lane j of the group is node j and the contraction
+// result arrives in the lane that owns the node.  N = 3 and N = 5 are packed:
+// max(Np, 3(N+1)) lanes per element (12 and 21: five and three elements per
+// wave instead of four and two), the contraction result goes through a small
+// LDS transpose, and the node columns span (Np + 15) / 16 tiles of 16.
+constexpr bool mfma_compact(int N) { return N == 3 || N == 5; }
+constexpr int mfma_lanes(int N) {
+    return mfma_compact(N) ? ((N + 1) * (N + 2) / 2 > 3 * (N + 1) ? (N + 1) * (N + 2) / 2 : 3 * (N + 1)) : 16;
+}
+constexpr int mfma_tiles(int N) { return ((N + 1) * (N + 2) / 2 + 15) / 16; }
 
 // K layout of the matrix-core contraction (N <= 5): Dr columns 0..Np-1, Ds
 // columns Np..2Np-1, zero padding to mfma_kv(N) (a multiple of 4), LIFT

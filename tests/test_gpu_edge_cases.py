@@ -135,7 +135,7 @@ def test_multirate_block_shapes_bitwise():
     _require_gpu()
     wl = W.c3(n0=2)
     runs = []
-    for epb in (4, 8, 16):
+    for epb in (5, 10, 20):   # N = 3: five 12-lane elements per wave
         g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
         g.advance(5)
         runs.append(g.get_state(0))

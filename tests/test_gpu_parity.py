@@ -291,23 +291,23 @@ def test_multirate_graph_matches_eager(path):
 @pytest.mark.parametrize("path", PATHS + ["fused_bf16x6"])
 def test_degree5_reduced_c4(path):
     """The N = 5 precision workload (16 Fourier modes, fully wet) on a reduced
-    128x64x2 mesh for 30 steps; on the matrix cores an element takes 32 lanes
-    and the 21 nodes two column tiles."""
+    128x64x2 mesh for 30 steps; on the matrix cores an element takes 21 lanes
+    (three per wave) and its 21 node columns two tiles."""
     _compare(f"c4-small-{path}", W.c4(nx=128, ny=64), 30, precision=path)
 
 
 def test_degree5_bf16x3_and_block_shapes():
     """N = 5 with the two-part BF16 split (its own tolerance) and the three
-    launch shapes of the 32-lane kernel (2, 4, 8 elements per block), which
+    launch shapes of the 21-lane kernel (3, 6, 12 elements per block), which
     agree bit for bit."""
     _require_gpu()
     _compare("c4-small-bf16x3", W.c4(nx=128, ny=64), 30, precision="fused_bf16x3", tol=BF16_TOL,
              tol_m=BF16_TOL)
     wl = W.c4(nx=32, ny=16)
-    ref = gpu_solver(wl, precision="fused_mfma32", elems_per_block=8)
+    ref = gpu_solver(wl, precision="fused_mfma32", elems_per_block=12)
     ref.advance(12)
     want = ref.get_state(0)
-    for epb in (2, 4):
+    for epb in (3, 6):
         g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
         g.advance(12)
         for x, y in zip(g.get_state(0), want):
