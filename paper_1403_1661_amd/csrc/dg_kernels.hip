@@ -1154,7 +1154,9 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const int tid = threadIdx.x;
     const int t = tid & 3;
     const int lane = tid & 63, qb4 = lane & ~3;
-    const int k = a.k_begin + blockIdx.x * 64 + (tid >> 2);
+    // XCD-contiguous block order, as in the step kernel: the neighbour records
+    // a mesh row away are then mostly in the same XCD's L2
+    const int k = a.k_begin + xcd_remap(blockIdx.x, gridDim.x) * 64 + (tid >> 2);
     if (k >= a.k_end) return;   // the whole quad leaves together
     const unsigned K = (unsigned)a.K;
     const int ed = t < 3 ? t : 0;   // lane 3 shadows edge 0 and is ignored
