@@ -12,10 +12,12 @@ timed region.
 
 Prints one JSON line: node-updates/s (value), the roofline of the fused step
 kernel (algorithmic bytes over its HIP-event time, against 8 TB/s), the
-plain (unfused) FP32 path on the same GPU, relative L2 against the FP64
-oracle after the configured 500 steps of the default workload (when the
-stored oracle samples are present), and the oracle's own throughput on this
-host's cores (default workload).
+plain (unfused) FP32 path and the other fused contraction engines (vector
+ALU, FP32 matrix cores, two- and three-part BF16 splits) on the same GPU,
+relative L2 against the FP64 oracle after the configured 500 steps of the
+default workload for each engine (when the stored oracle samples are
+present), the measured stream-copy ceiling, and the oracle's own throughput
+on this host's cores (default workload).
 """
 from __future__ import annotations
 
@@ -248,6 +250,23 @@ def main():
         plain = {"value": per_step * steps / tp, "ms_per_step": 1e3 * tp / steps}
         del p
 
+    # the other fused contraction engines on the same workload (same timing,
+    # and their accuracy against the stored oracle samples on the full C2 run)
+    engines = None
+    if not args.no_plain:
+        engines = {}
+        for prec in ("fused_fp32", "fused_mfma32", "fused_bf16x3", "fused_bf16x6"):
+            if prec == args.precision:
+                continue
+            e = make_solver(wl, prec, tune=not args.no_tune)
+            e.advance(warmup)
+            te = timed(e, steps, torch)
+            entry = {"value": per_step * steps / te, "ms_per_step": 1e3 * te / steps}
+            if args.workload == "c2" and warmup + steps == wl.steps:
+                entry["rel_l2_vs_oracle"] = rel_l2_vs_golden(e, wl)
+            engines[prec] = entry
+            del e
+
     kname = "step_mfma_kernel" if args.precision in ("fused_mfma32", "fused_bf16x3", "fused_bf16x6") \
         else "step_kernel"
     traffic = measured_traffic(args.precision) if args.workload == "c2" else None
@@ -278,6 +297,7 @@ def main():
                      "elements_per_launch": elems, "bytes_per_launch": bytes_launch},
         "plain_fp32": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "engines": engines,
         "rel_l2_vs_oracle": accuracy,
         "diagnostics": {"mass": diag["mass"], "min_depth": diag["min_depth"],
                         "pp_counts": diag["pp_counts"], "tvb_counts": diag["tvb_counts"],

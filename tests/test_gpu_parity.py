@@ -108,6 +108,15 @@ def test_low_orders_wetdry(path, N):
     assert g.diagnostics(0)["min_depth"] >= 0.0
 
 
+@pytest.mark.parametrize("path", ["plain_fp32", "fused_fp32"])
+def test_degree6_vector_alu_paths(path):
+    """N = 6 (28 nodes, 21 face nodes) runs only on the vector-ALU kernels
+    (the matrix-core kernel stops at N = 5): the small wet/dry beach, 40
+    steps against the oracle."""
+    g, o, q = _compare(f"wetdry-N6-{path}", W.small_wetdry(n=8, N=6), 40, precision=path, flip_frac=0.01)
+    assert g.diagnostics(0)["min_depth"] >= 0.0
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("path", PATHS)
 def test_lake_at_rest_exact_on_gpu(path, N):
