@@ -85,6 +85,12 @@ typedef struct dg_mesh_desc {
     const double* vy;
     int32_t n_elements;
     const int32_t* etov;
+    /* optional per-face boundary tags, K x 3 in the order of etov's faces
+     * (face f joins vertices f and f+1): 0 = interior where another element
+     * shares the face, wall otherwise; 1 = reflective wall even where the
+     * face is shared (both sides become walls: an internal barrier).  NULL
+     * = all 0.  Any other value is DG_EMESH.  Copied during dg_create. */
+    const int8_t* bc;
 } dg_mesh_desc;
 
 typedef struct dg_params {

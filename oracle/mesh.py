@@ -25,6 +25,7 @@ Test infrastructure only (see the package header).
 from __future__ import annotations
 
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -38,8 +39,10 @@ class MeshError(ValueError):
     pass
 
 
-def connect(etov: np.ndarray):
-    """EToE, EToF and wall flags from the element-to-vertex table."""
+def connect(etov: np.ndarray, bc: Optional[np.ndarray] = None):
+    """EToE, EToF and wall flags from the element-to-vertex table.  ``bc``
+    (K, 3), optional: 1 makes a face a reflective wall even where another
+    element shares it (then on both sides); 0 leaves it to the matching."""
     K = etov.shape[0]
     etoe = np.repeat(np.arange(K, dtype=np.int64)[:, None], 3, axis=1)
     etof = np.tile(np.arange(3, dtype=np.int64), (K, 1))
@@ -67,6 +70,16 @@ def connect(etov: np.ndarray):
     wall = np.zeros((K, 3), dtype=bool)
     for (k, f, _, _) in open_faces.values():
         wall[k, f] = True
+    if bc is not None:
+        bc = np.asarray(bc)
+        if bc.shape != (K, 3) or not np.all((bc == 0) | (bc == 1)):
+            raise MeshError("boundary tags must be (K, 3) with values 0 or 1")
+        for k, f in zip(*np.nonzero(bc == 1)):
+            if wall[k, f]:
+                continue
+            k2, f2 = etoe[k, f], etof[k, f]
+            etoe[k, f], etof[k, f], wall[k, f] = k, f, True
+            etoe[k2, f2], etof[k2, f2], wall[k2, f2] = k2, f2, True
     return etoe, etof, wall
 
 
@@ -95,7 +108,7 @@ class Mesh:
     vmapP: np.ndarray     # (K, 3*Nfp) flat index of the exterior node (self for walls)
 
 
-def build_mesh(vx, vy, etov, ref: RefElement) -> Mesh:
+def build_mesh(vx, vy, etov, ref: RefElement, bc=None) -> Mesh:
     vx = np.asarray(vx, dtype=np.float64)
     vy = np.asarray(vy, dtype=np.float64)
     etov = np.asarray(etov, dtype=np.int64)
@@ -127,7 +140,7 @@ def build_mesh(vx, vy, etov, ref: RefElement) -> Mesh:
                + (1 + s)[None, :] * x3[:, None])
     y = 0.5 * (-(r + s)[None, :] * y1[:, None] + (1 + r)[None, :] * y2[:, None]
                + (1 + s)[None, :] * y3[:, None])
-    etoe, etof, wall = connect(etov)
+    etoe, etof, wall = connect(etov, bc)
     Nfp = ref.Nfp
     vmapP = np.empty((K, 3 * Nfp), dtype=np.int64)
     for f in range(3):

@@ -88,11 +88,11 @@ class Solver:
     """FP64 DG-SWE solver on one triangulation."""
 
     def __init__(self, vx, vy, etov, N: int, params: Optional[Params] = None,
-                 ghost: Optional[Callable] = None):
+                 ghost: Optional[Callable] = None, bc=None):
         self.p = params or Params()
         self.N = N
         self.ref = reference_element(N)
-        self.mesh: Mesh = build_mesh(vx, vy, etov, self.ref)
+        self.mesh: Mesh = build_mesh(vx, vy, etov, self.ref, bc)
         self.levels = assign_levels(self.mesh, self.p.max_levels)
         self.stencil = tvb_stencil(self.mesh)
         self.ghost = ghost

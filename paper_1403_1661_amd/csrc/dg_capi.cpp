@@ -231,7 +231,7 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
             return fail(DG_EINVAL, "instance " + std::to_string(i) + ": null or empty mesh");
         std::string err;
         try {
-            err = build_host_mesh(m.n_vertices, m.vx, m.vy, m.n_elements, m.etov, h->inst[i].mesh);
+            err = build_host_mesh(m.n_vertices, m.vx, m.vy, m.n_elements, m.etov, m.bc, h->inst[i].mesh);
         } catch (const std::bad_alloc&) {
             return fail(DG_ENOMEM, "out of host memory");
         }

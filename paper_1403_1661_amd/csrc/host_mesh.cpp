@@ -24,7 +24,7 @@
 namespace dgswe {
 
 std::string build_host_mesh(int nv, const double* vx, const double* vy, int K,
-                            const int32_t* etov, HostMesh& m) {
+                            const int32_t* etov, const int8_t* bc, HostMesh& m) {
     if (nv < 3 || K < 1 || !vx || !vy || !etov) return "empty or null mesh";
     m.K = K;
     m.Nv = nv;
@@ -98,6 +98,18 @@ std::string build_host_mesh(int nv, const double* vx, const double* vy, int K,
             m.wall[3 * k2 + f2] = 0;
             closed.emplace(key, 1);
         }
+    }
+    // tagged walls: a shared face tagged on either side becomes a wall on both
+    if (bc) {
+        for (int k = 0; k < K; ++k)
+            for (int f = 0; f < 3; ++f) {
+                const int8_t t = bc[3 * k + f];
+                if (t != 0 && t != 1) return "boundary tag of element " + std::to_string(k) + " is not 0 or 1";
+                if (t == 0 || m.wall[3 * k + f]) continue;
+                const int k2 = m.etoe[3 * k + f], f2 = m.etof[3 * k + f];
+                m.etoe[3 * k + f] = k; m.etof[3 * k + f] = int8_t(f); m.wall[3 * k + f] = 1;
+                m.etoe[3 * k2 + f2] = k2; m.etof[3 * k2 + f2] = int8_t(f2); m.wall[3 * k2 + f2] = 1;
+            }
     }
     return "";
 }

@@ -27,8 +27,9 @@ struct HostMesh {
 };
 
 // Returns "" on success, else an error message (malformed mesh).
+// bc: optional K x 3 face tags (0 = interior where shared, 1 = wall)
 std::string build_host_mesh(int nv, const double* vx, const double* vy, int K,
-                            const int32_t* etov, HostMesh& m);
+                            const int32_t* etov, const int8_t* bc, HostMesh& m);
 void assign_levels(HostMesh& m, int max_levels);
 void build_tvb_stencil(HostMesh& m);
 void node_coords(const HostMesh& m, const RefElement& re, double* x, double* y);

@@ -44,7 +44,7 @@ class DGError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("vx", C.POINTER(C.c_double)),
                 ("vy", C.POINTER(C.c_double)), ("n_elements", C.c_int32),
-                ("etov", C.POINTER(C.c_int32))]
+                ("etov", C.POINTER(C.c_int32)), ("bc", C.POINTER(C.c_int8))]
 
 
 class Params(C.Structure):
@@ -149,7 +149,9 @@ class Solver:
         self.params = default_params(N, **params)
         self._keep = []
         descs = (MeshDesc * len(meshes))()
-        for i, (vx, vy, etov) in enumerate(meshes):
+        for i, mesh in enumerate(meshes):
+            # (vx, vy, etov) or (vx, vy, etov, bc) with bc the (K, 3) face tags
+            vx, vy, etov = mesh[:3]
             vx = np.ascontiguousarray(vx, dtype=np.float64)
             vy = np.ascontiguousarray(vy, dtype=np.float64)
             ev = np.ascontiguousarray(etov, dtype=np.int32)
@@ -159,6 +161,11 @@ class Solver:
             descs[i].vy = _dptr(vy)
             descs[i].n_elements = ev.shape[0]
             descs[i].etov = ev.ctypes.data_as(C.POINTER(C.c_int32))
+            if len(mesh) > 3 and mesh[3] is not None:
+                bc = np.ascontiguousarray(mesh[3], dtype=np.int8)
+                assert bc.shape == ev.shape
+                self._keep.append(bc)
+                descs[i].bc = bc.ctypes.data_as(C.POINTER(C.c_int8))
         h = C.c_void_p()
         _check(self.lib.dg_create(descs, len(meshes), C.byref(self.params), C.byref(h)))
         self.h = h

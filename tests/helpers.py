@@ -14,7 +14,7 @@ from oracle.swe import Params, Solver as OracleSolver
 def oracle_solver(wl, inst=0, **kw):
     ins = wl.instances[inst]
     p = Params(g=wl.g, cfl=kw.pop("cfl", wl.cfl), max_levels=kw.pop("max_levels", wl.max_levels), **kw)
-    s = OracleSolver(ins.vx, ins.vy, ins.etov, wl.N, p)
+    s = OracleSolver(ins.vx, ins.vy, ins.etov, wl.N, p, bc=ins.bc)
     x, y = s.nodes()
     B = s.interpolate(ins.bathymetry)
     h, hu, hv = ins.initial(x, y)
@@ -25,7 +25,7 @@ def oracle_solver(wl, inst=0, **kw):
 def gpu_solver(wl, precision="fused_fp32", insts=None, **kw):
     from paper_1403_1661_amd import dgswe
     insts = list(range(len(wl.instances))) if insts is None else insts
-    meshes = [(wl.instances[i].vx, wl.instances[i].vy, wl.instances[i].etov) for i in insts]
+    meshes = [(wl.instances[i].vx, wl.instances[i].vy, wl.instances[i].etov, wl.instances[i].bc) for i in insts]
     params = dict(g=wl.g, cfl=wl.cfl, max_levels=wl.max_levels, precision=precision)
     params.update(kw)
     s = dgswe.Solver(meshes, wl.N, **params)

@@ -44,18 +44,20 @@ def test_reference_element_matches_oracle(N):
     assert np.array_equal(s.reference(5).astype(int), ref.fmask)
 
 
-@pytest.mark.parametrize("case", ["c1", "wetdry", "c3small"])
+@pytest.mark.parametrize("case", ["c1", "wetdry", "c3small", "barrier"])
 def test_mesh_setup_matches_oracle(case):
     if case == "c1":
         wl, L = W.c1(), 1
     elif case == "wetdry":
         wl, L = W.small_wetdry(n=12, N=4), 1
+    elif case == "barrier":   # tagged internal walls
+        wl, L = W.barrier_basin(n=16, N=3), 1
     else:
         wl, L = W.c3(n0=3), 4
     ins = wl.instances[0]
-    s = dgswe.Solver([(ins.vx, ins.vy, ins.etov)], wl.N, max_levels=L)
+    s = dgswe.Solver([(ins.vx, ins.vy, ins.etov, ins.bc)], wl.N, max_levels=L)
     ref = reference_element(wl.N)
-    m = build_mesh(ins.vx, ins.vy, ins.etov, ref)
+    m = build_mesh(ins.vx, ins.vy, ins.etov, ref, ins.bc)
     etoe, etof = s.connectivity(0)
     assert np.array_equal(etoe, m.etoe)
     assert np.array_equal(etof, m.etof)
@@ -70,6 +72,29 @@ def test_mesh_setup_matches_oracle(case):
     pair, alpha = s.tvb_stencil(0)
     assert np.array_equal(pair.astype(int), st.pair)
     assert np.max(np.abs(alpha - st.alpha)) < 1e-13
+
+
+def test_boundary_tags():
+    """A tagged shared face becomes a wall on both sides (EToE = self);
+    tags other than 0 and 1 are mesh errors."""
+    wl = W.barrier_basin(n=8, N=2)
+    ins = wl.instances[0]
+    s = dgswe.Solver([(ins.vx, ins.vy, ins.etov, ins.bc)], 2)
+    etoe, etof = s.connectivity(0)
+    plain = dgswe.Solver([(ins.vx, ins.vy, ins.etov)], 2)
+    etoe0, _ = plain.connectivity(0)
+    K = ins.etov.shape[0]
+    tagged = ins.bc.astype(bool)
+    assert tagged.sum() > 0
+    self_ref = etoe == np.arange(K)[:, None]
+    assert np.all(self_ref[tagged])                      # tagged faces are walls
+    assert np.all(etoe0[tagged] != np.arange(K)[:, None].repeat(3, 1)[tagged])   # they were shared
+    assert np.array_equal(etoe[~tagged], etoe0[~tagged])   # the rest is unchanged
+    bad = ins.bc.copy()
+    bad[0, 0] = 2
+    with pytest.raises(dgswe.DGError) as e:
+        dgswe.Solver([(ins.vx, ins.vy, ins.etov, bad)], 2)
+    assert e.value.code == -2
 
 
 def test_ensemble_sizes():

@@ -142,3 +142,34 @@ def test_multirate_block_shapes_bitwise():
     for other in runs[1:]:
         for x, y in zip(other, runs[0]):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_internal_barrier(path):
+    """Tagged internal walls (dg_mesh_desc.bc): with an opening the HIP path
+    follows the oracle; with the wall closed the undisturbed basin stays
+    bitwise at rest and keeps its mass."""
+    _require_gpu()
+    wl = W.barrier_basin(n=16, N=3)
+    g = gpu_solver(wl, precision=path)
+    o = oracle_solver(wl)
+    etoe, _ = g.connectivity(0)
+    assert np.array_equal(etoe, o.mesh.etoe)
+    g.advance(60)
+    o.run(60)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    log(f"[barrier] {path} relL2 h={err['h']:.3e} m={err['m']:.3e}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert flag_flips(g.flags(0), o.flags) == (0, 0)
+
+    closed = W.barrier_basin(n=16, N=3, gap=(2.0, 2.0))
+    g = gpu_solver(closed, precision=path)
+    g.prepare()   # the initial limiting; the state is on the device from here on
+    h0, hu0, hv0 = g.get_state(0)
+    g.advance(60)
+    h, hu, hv = g.get_state(0)
+    x, _ = g.node_coords(0)
+    right = x.mean(axis=1) > 0.5
+    assert np.array_equal(h[right], h0[right])
+    assert np.all(hu[right] == 0.0) and np.all(hv[right] == 0.0)
+    assert np.max(np.abs(hu[~right])) > 1e-3

@@ -57,6 +57,7 @@ class Instance:
     bathymetry: Callable[[np.ndarray, np.ndarray], np.ndarray]
     initial: Callable[[np.ndarray, np.ndarray], tuple]   # -> (h, hu, hv)
     label: str = ""
+    bc: Optional[np.ndarray] = None   # (K, 3) face tags, 1 = wall (internal barriers)
 
 
 @dataclass
@@ -341,6 +342,33 @@ def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Wor
 
     return Workload("wetdry", N, [Instance(vx, vy, etov, bath, init, "wetdry")], steps=steps,
                     cfl=0.2, seed=seed, notes="small beach")
+
+
+def barrier_basin(n: int = 16, N: int = 3, gap: tuple = (0.375, 0.625), steps: int = 60) -> Workload:
+    """Unit square with an internal wall along x = 1/2 (tagged faces) that
+    leaves an opening for gap[0] < y < gap[1]; flat bed at depth 1 and a
+    Gaussian hump cut off at x = 1/2, so the right basin starts at rest.  n
+    must be even so that x = 1/2 is a grid line."""
+    if n % 2:
+        raise ValueError("n must be even")
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0)
+    a = etov
+    b = np.roll(etov, -1, axis=1)
+    on_line = (np.abs(vx[a] - 0.5) < 1e-12) & (np.abs(vx[b] - 0.5) < 1e-12)
+    ymid = 0.5 * (vy[a] + vy[b])
+    bc = (on_line & ((ymid < gap[0]) | (ymid > gap[1]))).astype(np.int8)
+
+    def bath(x, y):
+        return _zeros_like(np.asarray(x, dtype=np.float64))
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        hump = 0.1 * np.exp(-100.0 * ((x - 0.25) ** 2 + (y - 0.5) ** 2))
+        h = 1.0 + np.where(x < 0.5, hump, 0.0)   # the right basin starts exactly at rest
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload("barrier", N, [Instance(vx, vy, etov, bath, init, "barrier", bc=bc)], steps=steps,
+                    cfl=0.5, notes=f"barrier basin {n}x{n}x2, N={N}, opening {gap}")
 
 
 # ---------------------------------------------------------------------------
