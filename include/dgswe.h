@@ -55,10 +55,11 @@ extern "C" {
 #define DG_PLAIN_FP32     0  /* separate RHS, update and limiter kernels, FP32 VALU  */
 #define DG_FUSED_FP32     1  /* fused RHS+AB3+positivity kernel, FP32 VALU matvecs   */
 #define DG_FUSED_MFMA32   2  /* fused kernel, [Dr Ds LIFT] contraction on FP32 MFMA  */
+                             /* (N <= 5)                                           */
 #define DG_FUSED_BF16X3   3  /* fused kernel, BF16 MFMA, operands split in 2 parts,  */
-                             /* 3 products, FP32 accumulate (N <= 4)               */
+                             /* 3 products, FP32 accumulate (N <= 5)               */
 #define DG_FUSED_BF16X6   4  /* fused kernel, BF16 MFMA, operands split in 3 parts,  */
-                             /* 6 products, FP32 accumulate (N <= 4)               */
+                             /* 6 products, FP32 accumulate (N <= 5)               */
 
 /* limiter switches (dg_params.limiter_mask) */
 #define DG_LIMIT_PP   1      /* positivity limiter, Algorithm 5.2         */
@@ -105,11 +106,14 @@ typedef struct dg_params {
     double tvb_nu;          /* TVB factor on the neighbour difference (>= 1)          */
     int32_t limiter_mask;   /* DG_LIMIT_* bits                                        */
     int32_t max_levels;     /* multi-rate levels (1 = single rate AB3), 1..8          */
-    int32_t precision;      /* DG_PLAIN_FP32 .. DG_FUSED_BF16X3                        */
+    int32_t precision;      /* DG_PLAIN_FP32 .. DG_FUSED_BF16X6                        */
     int32_t dry_literal;    /* 1: dry element gets h = h0 (Algorithm 5.2 as printed); */
                             /* 0: h = max(mean, 0), which conserves mass              */
     int32_t use_graph;      /* 1: replay dg_advance steps from a captured hipGraph    */
-    int32_t elems_per_block;/* 0 = default for N and path                             */
+    int32_t elems_per_block;/* 0 = default for N and path; matrix-core paths: 1, 2 or */
+                            /* 4 waves of 64/lanes elements (N = 1, 2, 4: 4, 8, 16;   */
+                            /* N = 3: 5, 10, 20; N = 5: 3, 6, 12); VALU paths:        */
+                            /* floor(256 / Np); anything else is DG_EINVAL            */
 } dg_params;
 
 /* Fill *p with the defaults: g 9.81, cfl 0.5, h0 = eps = 1e-5, hvel 1e-3, M 10, nu 1.5,
@@ -176,7 +180,8 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 
 /* Autotuner (launch shape of the step kernel).  Times the step kernel of
  * the next tick `reps` times for each elements-per-block candidate of the
- * path (matrix-core path: 4, 8 and 16; the VALU paths have one shape) and
+ * path (matrix-core paths: 1, 2 and 4 waves, see elems_per_block; the VALU
+ * paths have one shape) and
  * keeps the fastest in the solver's parameters.  The state, history, flags
  * and counters are left as they were.  Writes min(max_out, candidates) pairs (elements per
  * block, average microseconds) to epb/us and the candidate count to *n_out.
