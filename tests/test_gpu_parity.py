@@ -198,10 +198,10 @@ def test_bench_config_full_size_first_steps(path):
 
 @pytest.mark.parametrize("path", PATHS + ["fused_bf16x3", "fused_bf16x6"])
 def test_bench_config_500_steps(path):
-    """The bench workload for its configured 500 steps against the stored
-    FP64 oracle states of 1024 sampled elements (written by
-    tests/golden/make_golden.py): relative L2 <= 1e-5 on the sample,
-    mass within FP32 rounding of the oracle's."""
+    """The bench workload for its configured 500 steps, in the autotuned
+    launch shape, against the stored FP64 oracle states of 1024 sampled
+    elements (written by tests/golden/make_golden.py): relative L2 <= 1e-5 on
+    the sample, mass within FP32 rounding of the oracle's."""
     import os
     _require_gpu()
     golden = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_samples.npz")
@@ -211,6 +211,8 @@ def test_bench_config_500_steps(path):
     wl = W.c2()
     log(f"[c2-500] K=131072 N=4 steps=500 path={path}")
     g = gpu_solver(wl, precision=path)
+    g.prepare()
+    g.autotune(reps=3)   # the launch shape bench.py times
     g.advance(int(z["steps"]))
     h, hu, hv = g.get_state(0)
     idx = z["elements"]
