@@ -70,7 +70,8 @@ struct dg_solver {
     bool bound = false, prepared = false;
     int device = 0;
     // host staging (sorted order, FP32)
-    std::vector<float> geo, stencil, Bh, Qh, dBh;   // dBh: [2][K*Np] bed gradient   // Qh: [4][K*Np] (eta hi, hu, hv, eta lo); Bh, eta relative to the datum
+    std::vector<float> geo, stencil, Bh, Qh, dBh;   // dBh: [2][K*Np] bed gradient; Qh: [3][K*Np] (eta hi, hu, hv); Bh, eta relative to the datum
+    std::vector<int16_t> Ql;                         // [K*Np] eta lo, 16-bit (see lo_encode)
     std::vector<double> B64;                   // bed elevation, FP64, sorted order
     std::vector<int> conn;
     // time stepping state
@@ -108,6 +109,21 @@ static float bf16_value(uint16_t b) {
     return f;
 }
 
+// The level's low word travels as a 16-bit integer in units of 2^-15 ulp(hi)
+// (ulp(hi) = 2^(e-24) with hi = m 2^e, 1/2 <= |m| < 1); the kernels use the
+// same encoding.
+static int16_t lo_encode(float hi, float lo) {
+    int e = 0;
+    std::frexp(hi, &e);
+    const float s = std::nearbyint(std::ldexp(lo, 39 - e));
+    return int16_t(std::fmin(std::fmax(s, -32767.f), 32767.f));
+}
+static float lo_decode(float hi, int16_t s) {
+    int e = 0;
+    std::frexp(hi, &e);
+    return std::ldexp(float(s), e - 39);
+}
+
 static int engine_of(int precision) {
     switch (precision) {
         case DG_FUSED_MFMA32: return ENGINE_MFMA_F32;
@@ -127,8 +143,9 @@ static void compute_layout(dg_solver* h) {
     };
     const size_t KNp = size_t(h->K) * h->Np, KnF = size_t(h->K) * h->nF;
     l.dyn_begin = o;
-    l.Q[0] = take(4 * KNp * 4);
-    l.Q[1] = take(4 * KNp * 4);
+    // state: eta hi, hu, hv (FP32) then the level's low word (16-bit)
+    l.Q[0] = take(14 * KNp);
+    l.Q[1] = take(14 * KNp);
     for (int s = 0; s < 3; ++s) l.R[s] = take(3 * KNp * 4);
     l.half = take(h->L > 1 ? 3 * KnF * 4 : 0);
     l.mrec = take(4 * size_t(h->K) * 8);
@@ -563,7 +580,8 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
     if (!I.has_B) return fail(DG_ESTATE, "set the bathymetry of the instance first");
     const int Np = h->Np;
     const size_t KNp = size_t(h->K) * Np;
-    if (h->Qh.empty()) h->Qh.assign(4 * KNp, 0.f);
+    if (h->Qh.empty()) h->Qh.assign(3 * KNp, 0.f);
+    if (h->Ql.empty()) h->Ql.assign(KNp, 0);
     double amax = 0.0, eta_sum = 0.0;
     long long n_wet = 0;
     for (int k = 0; k < I.mesh.K; ++k) {
@@ -612,7 +630,7 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
             h->Qh[dst] = es;
             h->Qh[KNp + dst] = float(hu[src]);
             h->Qh[2 * KNp + dst] = float(hv[src]);
-            h->Qh[3 * KNp + dst] = el;
+            h->Ql[dst] = lo_encode(es, el);
         }
     }
     double rmin = I.mesh.inradius[0];
@@ -826,6 +844,8 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
         h->nhist[q] = 0;
     }
     HIPCHECK(hipMemcpyAsync(h->ws + l.Q[0], h->Qh.data(), h->Qh.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->ws + l.Q[0] + 12 * h->Ql.size(), h->Ql.data(), h->Ql.size() * 2,
+                            hipMemcpyHostToDevice, s));
     h->steps = 0;
     for (auto& I : h->inst) I.time = 0.0;
     // Q0 = TVB(PP(Pi_H Q0)), first line of Algorithm 5.1
@@ -994,20 +1014,22 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
     const int Np = h->Np;
     const size_t KNp = size_t(h->K) * Np;
     const Inst& I = h->inst[inst];
-    std::vector<float> q(4 * KNp), b(KNp);
+    std::vector<float> q(3 * KNp), b(KNp);
+    std::vector<int16_t> ql(KNp);
     for (int l = 0; l < h->L; ++l) {
         const size_t b0 = size_t(h->lev_begin[l]) * Np, n = size_t(h->lev_end[l] - h->lev_begin[l]) * Np;
         if (!n) continue;
-        for (int c = 0; c < 4; ++c)
-            HIPCHECK(hipMemcpy(q.data() + c * KNp + b0, h->ws + h->lay.Q[h->parity[l]] + (c * KNp + b0) * 4,
-                               n * 4, hipMemcpyDeviceToHost));
+        const char* Q = h->ws + h->lay.Q[h->parity[l]];
+        for (int c = 0; c < 3; ++c)
+            HIPCHECK(hipMemcpy(q.data() + c * KNp + b0, Q + (c * KNp + b0) * 4, n * 4, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(ql.data() + b0, Q + 12 * KNp + b0 * 2, n * 2, hipMemcpyDeviceToHost));
     }
     HIPCHECK(hipMemcpy(b.data(), h->ws + h->lay.B, KNp * 4, hipMemcpyDeviceToHost));
     for (int k = 0; k < I.mesh.K; ++k) {
         const size_t sidx = size_t(h->inv[I.offset + k]);
         for (int j = 0; j < Np; ++j) {
             const size_t src = sidx * Np + j, dst = size_t(k) * Np + j;
-            hh[dst] = double(q[src]) - double(b[src]) + double(q[3 * KNp + src]);
+            hh[dst] = double(q[src]) - double(b[src]) + double(lo_decode(q[src], ql[src]));
             hu[dst] = double(q[KNp + src]);
             hv[dst] = double(q[2 * KNp + src]);
         }

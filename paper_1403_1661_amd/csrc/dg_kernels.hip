@@ -76,6 +76,18 @@ __device__ __forceinline__ void eta_add(float& hi, float& lo, float d) {
     lo = l - (hi - s);
 }
 
+// The low word is stored as a 16-bit integer in units of 2^-15 ulp(hi):
+// |lo| <= ulp(hi)/2 fits in +-2^14, and the stored pair keeps the level to
+// 2^-16 ulp(hi) (ulp(hi) = 2^(e-24) with hi = m 2^e, 1/2 <= |m| < 1).
+__device__ __forceinline__ short lo_encode(float hi, float lo) {
+    const int e = __builtin_amdgcn_frexp_expf(hi);
+    const float s = __builtin_rintf(__builtin_amdgcn_ldexpf(lo, 39 - e));
+    return (short)fminf(fmaxf(s, -32767.f), 32767.f);
+}
+__device__ __forceinline__ float lo_decode(float hi, short s) {
+    return __builtin_amdgcn_ldexpf((float)s, __builtin_amdgcn_frexp_expf(hi) - 39);
+}
+
 __device__ __forceinline__ void eta_split(double v, float& hi, float& lo) {
     hi = (float)v;
     lo = (float)(v - (double)hi);
@@ -156,7 +168,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         eta = Q[idx];
         hu = Q[KNp + idx];
         hv = Q[2 * KNp + idx];
-        lo = Q[3 * KNp + idx];
+        lo = lo_decode(eta, reinterpret_cast<const short*>(Q + 3 * KNp)[idx]);
         Bn = a.B[idx];
         sQ[0][tid] = eta;
         sQ[1][tid] = hu;
@@ -227,7 +239,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                     etaP = Q2[id2];
                     huP = Q2[KNp + id2];
                     hvP = Q2[2 * KNp + id2];
-                    loP = Q2[3 * KNp + id2];
+                    loP = lo_decode(etaP, reinterpret_cast<const short*>(Q2 + 3 * KNp)[id2]);
                 } else {
                     const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - j);
                     etaP = a.half[hid];
@@ -469,7 +481,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     Qo[idx] = out[0];
     Qo[KNp + idx] = out[1];
     Qo[2 * KNp + idx] = out[2];
-    Qo[3 * KNp + idx] = olo;
+    reinterpret_cast<short*>(Qo + 3 * KNp)[idx] = lo_encode(out[0], olo);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,6 +664,16 @@ struct BufF32 {
     __device__ __forceinline__ float ldb(unsigned byte_off, unsigned field_bytes) const {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)field_bytes, 0));
     }
+    // 16-bit field (the level's low word): element i at field_bytes + 2 i
+    __device__ __forceinline__ short ld16(unsigned i, unsigned field_bytes) const {
+        return (short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(i * 2u), (int)field_bytes, 0);
+    }
+    __device__ __forceinline__ short ldb16(unsigned byte_off, unsigned field_bytes) const {
+        return (short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)byte_off, (int)field_bytes, 0);
+    }
+    __device__ __forceinline__ void st16(unsigned i, unsigned field_bytes, short v) const {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)(i * 2u), (int)field_bytes, 0);
+    }
     __device__ __forceinline__ void st(unsigned i, unsigned field_bytes, float v) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(i * 4u), (int)field_bytes, 0);
     }
@@ -742,13 +764,14 @@ step_mfma_kernel(StepArgs a) {
     float* r_now = MULTI ? a.R[L.slot[0]] : a.r_now;
     const float* r_prev1 = MULTI ? a.R[L.slot[1]] : a.r_prev1;
     const float* r_prev2 = MULTI ? a.R[L.slot[2]] : a.r_prev2;
-    const BufF32 bQi(q_in, 4u * FB), bQo(q_out, 4u * FB), bB(a.B, FB), bdB(a.dB, 2u * FB);
+    const unsigned QB = 3u * FB + 2u * KNp;   // state buffer: hi, hu, hv (FP32), lo (16-bit)
+    const BufF32 bQi(q_in, QB), bQo(q_out, QB), bB(a.B, FB), bdB(a.dB, 2u * FB);
     const BufF32 bR0(r_now, 3u * FB), bR1(r_prev1, 3u * FB), bR2(r_prev2, 3u * FB);
     float r1[3], r2[3];
     const float eta = bQi.ld(idx, 0);
     const float hu = bQi.ld(idx, FB);
     const float hv = bQi.ld(idx, 2u * FB);
-    const float lo = bQi.ld(idx, 3u * FB);
+    const float lo = lo_decode(eta, bQi.ld16(idx, 3u * FB));
     const float Bn = bB.ld(idx, 0);
     const float dBx = bdB.ld(idx, 0);   // static bed gradient
     const float dBy = bdB.ld(idx, FB);
@@ -780,19 +803,20 @@ step_mfma_kernel(StepArgs a) {
         etaP = bQi.ld(id2, 0);
         huP = bQi.ld(id2, FB);
         hvP = bQi.ld(id2, 2u * FB);
-        loP = bQi.ld(id2, 3u * FB);
+        loP = lo_decode(etaP, bQi.ld16(id2, 3u * FB));
     } else {
         // the neighbour's level: its state buffer (one view spans both
         // parities) or, when it does not step at this tick, its half-step
         // traces
         const int l2 = level_of(a, nbc);
         if (((a.active_bits >> l2) & 1u) || a.half == nullptr) {
-            const BufF32 bQ2(a.Q[0], a.q_pair_bytes + 4u * FB);
-            const unsigned off = id2 * 4u + (((a.parity_bits >> l2) & 1u) ? a.q_pair_bytes : 0u);
+            const BufF32 bQ2(a.Q[0], a.q_pair_bytes + QB);
+            const unsigned par = ((a.parity_bits >> l2) & 1u) ? a.q_pair_bytes : 0u;
+            const unsigned off = id2 * 4u + par;
             etaP = bQ2.ldb(off, 0);
             huP = bQ2.ldb(off, FB);
             hvP = bQ2.ldb(off, 2u * FB);
-            loP = bQ2.ldb(off, 3u * FB);
+            loP = lo_decode(etaP, bQ2.ldb16(id2 * 2u + par, 3u * FB));
         } else {
             const unsigned hid = (unsigned)nbc * nF + f2 * Nfp + (Nfp - 1 - jj);
             etaP = bH.ld(hid, 0);
@@ -1138,7 +1162,7 @@ step_mfma_kernel(StepArgs a) {
     bQo.st(idx, 0, out[0]);
     bQo.st(idx, FB, out[1]);
     bQo.st(idx, 2u * FB, out[2]);
-    bQo.st(idx, 3u * FB, olo);
+    bQo.st16(idx, 3u * FB, lo_encode(out[0], olo));
 }
 
 // ---------------------------------------------------------------------------
@@ -1285,7 +1309,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         float hi, lo;
         eta_split(hval + (double)a.B[id], hi, lo);
         Qo[id] = hi;
-        Qo[3 * a.KNp + id] = lo;
+        reinterpret_cast<short*>(Qo + 3 * a.KNp)[id] = lo_encode(hi, lo);
         Qo[a.KNp + id] = (float)(qb[1] + D[1][0] * p0 + D[1][1] * p1 + D[1][2] * p2);
         Qo[2 * a.KNp + id] = (float)(qb[2] + D[2][0] * p0 + D[2][1] * p1 + D[2][2] * p2);
     }
@@ -1312,7 +1336,8 @@ __global__ void __launch_bounds__(256) diag_partial_kernel(DiagArgs a) {
         double wh = 0.0;
         for (int j = 0; j < a.Np; ++j) {
             const long long id = (long long)k * a.Np + j;
-            const double h = (double)Q[id] - (double)a.B[id] + (double)Q[3 * a.KNp + id];
+            const double h = (double)Q[id] - (double)a.B[id] +
+                             (double)lo_decode(Q[id], reinterpret_cast<const short*>(Q + 3 * a.KNp)[id]);
             wh += a.wfull[j] * h;
             hmin = fmin(hmin, h);
         }
@@ -1406,7 +1431,7 @@ static int dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0,
         }
         m.seg_block[kMaxLevels] = blocks;
         const long long qd = reinterpret_cast<const char*>(a.Q[1]) - reinterpret_cast<const char*>(a.Q[0]);
-        if (qd < 16 * a.KNp || qd + 16 * a.KNp >= (1ll << 32)) {
+        if (qd < 14 * a.KNp || qd + 14 * a.KNp >= (1ll << 32)) {
             std::snprintf(g_dev_err, sizeof(g_dev_err), "state buffers out of one 32-bit view");
             return -1;
         }

@@ -71,7 +71,8 @@ struct StepArgs {
     int k_begin, k_end;    // element range of this launch
     int nlev;
     LevelArgs lev[kMaxLevels];
-    float* Q[2];           // ping-pong state buffers [4][K*Np]: eta (hi), hu, hv, eta (lo)
+    float* Q[2];           // ping-pong state buffers: [3][K*Np] FP32 eta (hi), hu, hv, then
+                           // [K*Np] 16-bit eta (lo) at float offset 3 K*Np
     const float* B;        // [K*Np]
     const float* dB;       // [2][K*Np] dB/dx, dB/dy at the nodes (static, from FP64 on the host)
     float* R[3];           // ring slots [3][K*Np]
@@ -124,7 +125,7 @@ struct TvbArgs {
 struct DiagArgs {
     int K, Np, k_begin, k_end, inst;
     long long KNp;
-    const float* Q;        // state buffer [4][K*Np] (per element parity resolved by caller)
+    const float* Q;        // state buffer, layout of StepArgs::Q (per element parity resolved by caller)
     const float* Q2;       // second buffer
     const int* parity_of;  // null: all from Q; else per-level parity via lev table
     int nlev;
