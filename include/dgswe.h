@@ -114,11 +114,14 @@ typedef struct dg_params {
                             /* 4 waves of 64/lanes elements (N = 1, 2, 4: 4, 8, 16;   */
                             /* N = 3: 5, 10, 20; N = 5: 3, 6, 12); VALU paths:        */
                             /* floor(256 / Np); anything else is DG_EINVAL            */
+    double thin_cut;        /* >= 0; > 0: after the limiters, momentum is set to zero */
+                            /* at nodes whose depth is below thin_cut (thin films at  */
+                            /* shorelines; the paper is silent there).  0 = off       */
 } dg_params;
 
 /* Fill *p with the defaults: g 9.81, cfl 0.5, h0 = eps = 1e-5, hvel 1e-3, M 10, nu 1.5,
  * both limiters, single rate, DG_FUSED_FP32, mass-conserving dry branch,
- * graphs on. */
+ * graphs on, no thin-film momentum cut. */
 int32_t dg_default_params(int32_t N, dg_params* p);
 
 /* Validate and set up n_inst instances (n_inst > 1: an ensemble advanced

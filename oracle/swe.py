@@ -74,6 +74,7 @@ class Params:
     pp: bool = True
     tvb: bool = True
     dry_literal: bool = False  # literal dry branch h = h0 instead of max(hbar, 0)
+    thin_cut: float = 0.0      # > 0: momentum zeroed after the limiters where h < thin_cut
     max_levels: int = 1
 
 
@@ -365,7 +366,22 @@ class Solver:
         tv = np.zeros(K, dtype=np.uint8)
         if p.tvb:
             q, tv = self.tvb_limit(q, pp, active)
+        q = self.cut_thin_films(q, active)
         return q, StepFlags(pp, tv, neg)
+
+    def cut_thin_films(self, q, active=None):
+        """Optional thin-film rule (the paper is silent on velocities where
+        the depth is tiny): after both limiters, zero the momentum at nodes
+        whose depth is below thin_cut (elements that stepped only)."""
+        if self.p.thin_cut <= 0.0:
+            return q
+        thin = q[0] < self.p.thin_cut
+        if active is not None:
+            thin &= active[:, None]
+        q = q.copy()
+        q[1] = np.where(thin, 0.0, q[1])
+        q[2] = np.where(thin, 0.0, q[2])
+        return q
 
     # ------------------------------------------------------------ stepping
     def step(self):
@@ -451,6 +467,7 @@ class Solver:
         if p.tvb:
             q, tv_new = self.tvb_limit(q, pp, active)
             tv = np.where(active, tv_new, prev_tv)
+        q = self.cut_thin_films(q, active)
         return q, StepFlags(pp, tv, neg)
 
     # --------------------------------------------------------- diagnostics

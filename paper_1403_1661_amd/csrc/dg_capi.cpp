@@ -205,6 +205,7 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
     if (!meshes || !p || !out || n_inst < 1) return fail(DG_EINVAL, "null argument or n_inst < 1");
     *out = nullptr;
     if (p->N < 1 || p->N > 6) return fail(DG_EINVAL, "N must be in 1..6");
+    if (!(p->thin_cut >= 0)) return fail(DG_EINVAL, "thin_cut must be >= 0");
     if (!(p->g > 0) || !(p->cfl > 0) || !(p->h0 > 0) || !(p->eps >= 0) || !(p->hvel > 0) ||
         !(p->tvb_M >= 0) ||
         !(p->tvb_nu >= 1.0))
@@ -683,6 +684,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.h0 = float(h->p.h0);
     a.eps = float(h->p.eps);
     a.hvel = float(h->p.hvel);
+    a.thin_cut = float(h->p.thin_cut);
     a.pp_on = (h->p.limiter_mask & DG_LIMIT_PP) ? 1 : 0;
     a.dry_literal = h->p.dry_literal;
     return a;
@@ -729,6 +731,7 @@ static TvbArgs tvb_args(dg_solver* h, const StepArgs& sa) {
     t.g = h->p.g;
     t.h0 = h->p.h0;
     t.nu = h->p.tvb_nu;
+    t.thin_cut = h->p.thin_cut;
     return t;
 }
 

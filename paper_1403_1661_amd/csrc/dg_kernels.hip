@@ -477,6 +477,10 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 out[c] = (float)val;
         }
     }
+    if (a.thin_cut > 0.f && (out[0] - Bn) + olo < a.thin_cut) {   // thin film: no momentum
+        out[1] = 0.f;
+        out[2] = 0.f;
+    }
     float* Qo = a.Q[1 - L.parity];
     Qo[idx] = out[0];
     Qo[KNp + idx] = out[1];
@@ -1159,6 +1163,10 @@ step_mfma_kernel(StepArgs a) {
                 out[c] = (float)val;
         }
     }
+    if (a.thin_cut > 0.f && (out[0] - Bn) + olo < a.thin_cut) {   // thin film: no momentum
+        out[1] = 0.f;
+        out[2] = 0.f;
+    }
     bQo.st(idx, 0, out[0]);
     bQo.st(idx, FB, out[1]);
     bQo.st(idx, 2u * FB, out[2]);
@@ -1310,8 +1318,9 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         eta_split(hval + (double)a.B[id], hi, lo);
         Qo[id] = hi;
         reinterpret_cast<short*>(Qo + 3 * a.KNp)[id] = lo_encode(hi, lo);
-        Qo[a.KNp + id] = (float)(qb[1] + D[1][0] * p0 + D[1][1] * p1 + D[1][2] * p2);
-        Qo[2 * a.KNp + id] = (float)(qb[2] + D[2][0] * p0 + D[2][1] * p1 + D[2][2] * p2);
+        const bool thin = a.thin_cut > 0.0 && hval < a.thin_cut;   // thin film: no momentum
+        Qo[a.KNp + id] = thin ? 0.f : (float)(qb[1] + D[1][0] * p0 + D[1][1] * p1 + D[1][2] * p2);
+        Qo[2 * a.KNp + id] = thin ? 0.f : (float)(qb[2] + D[2][0] * p0 + D[2][1] * p1 + D[2][2] * p2);
     }
     if (t == 0) a.flags[k] = pp | (code << 2);
 }

@@ -100,6 +100,7 @@ struct StepArgs {
     unsigned long long* counters;  // [0] negative-mean events
     DevOps ops;
     float g, h0, eps, hvel;
+    float thin_cut;        // > 0: momentum zeroed at output nodes with depth below it
     int pp_on, dry_literal;
 };
 
@@ -120,6 +121,7 @@ struct TvbArgs {
     uint8_t* flags;
     const double* phi;     // 3 x Np
     double g, h0, nu;
+    double thin_cut;       // as StepArgs::thin_cut
 };
 
 struct DiagArgs {

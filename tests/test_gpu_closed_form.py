@@ -124,3 +124,36 @@ def test_rarefaction_convergence_paper_settings(N):
     assert eoc_g >= want_g
     if want_l is not None:
         assert eoc_l >= want_l
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_thin_cut_parity(path):
+    """The optional thin-film rule (thin_cut = 1e-3) at the default
+    desingularisation depth: the oscillating lake for an eighth of a period
+    against the oracle with the same rule, and still water with a shoreline
+    that stays bounded for 1000 steps."""
+    _require_gpu()
+    from helpers import gpu_solver, oracle_solver
+    wl = W.oscillating_lake(16, 2)
+    steps = None
+    g = gpu_solver(wl, precision=path, thin_cut=1e-3)
+    o = oracle_solver(wl, thin_cut=1e-3)
+    steps = int(round(0.125 * wl.extra["period"] / o.dt_min))
+    g.advance(steps)
+    o.run(steps)
+    q = np.stack(g.get_state(0))
+    err = rel_l2(o, q, o.q)
+    pp, tv = flag_flips(g.flags(0), o.flags)
+    log(f"[thin-cut] lake {path} {steps} steps h={err['h']:.3e} m={err['m']:.3e} flips pp={pp} tvb={tv}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    thin = q[0] < 1e-3
+    assert np.all(q[1][thin] == 0.0) and np.all(q[2][thin] == 0.0)
+
+    wl = W.shoreline_lake(n=16, N=2)
+    g = gpu_solver(wl, precision=path, thin_cut=1e-3)
+    g.advance(1000)
+    h, hu, hv = g.get_state(0)
+    d = g.diagnostics(0)
+    log(f"[thin-cut] shoreline {path} max|hu|={np.abs(hu).max():.3e} min h={d['min_depth']:.3e}")
+    assert np.all(np.isfinite(h)) and d["min_depth"] >= 0.0
+    assert max(np.abs(hu).max(), np.abs(hv).max()) <= 1e-2

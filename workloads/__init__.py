@@ -371,6 +371,25 @@ def barrier_basin(n: int = 16, N: int = 3, gap: tuple = (0.375, 0.625), steps: i
                     cfl=0.5, notes=f"barrier basin {n}x{n}x2, N={N}, opening {gap}")
 
 
+def shoreline_lake(n: int = 16, N: int = 2, steps: int = 600) -> Workload:
+    """Still water of depth 0.1 in the paraboloid B = 0.1 (x^2 + y^2) on
+    [-2, 2]^2: the shoreline r = 1 crosses elements, so partially wet
+    elements are not a discrete steady state (a thin-film stress case)."""
+    vx, vy, etov = structured_mesh(n, n, -2.0, 2.0, -2.0, 2.0)
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return on_bed_grid(0.1 * (x * x + y * y))
+
+    def init(x, y):
+        h = np.maximum(0.0, 0.1 - bath(x, y))
+        return h, _zeros_like(h), _zeros_like(h)
+
+    return Workload("shoreline", N, [Instance(vx, vy, etov, bath, init, "shoreline")], steps=steps,
+                    cfl=0.2, notes=f"still water with a shoreline {n}x{n}x2, N={N}")
+
+
 # ---------------------------------------------------------------------------
 # Closed-form wet/dry cases of the paper's numerical section.  Each workload
 # carries ``extra["exact"](x, y, t) -> (h, hu, hv)`` (the printed solution),
