@@ -108,6 +108,18 @@ def test_low_orders_wetdry(path, N):
     assert g.diagnostics(0)["min_depth"] >= 0.0
 
 
+@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("path", ["fused_bf16x3", "fused_bf16x6"])
+def test_bf16_engines_low_orders(path, N):
+    """The BF16 split engines at orders 1-3 (N = 3 in the packed 12-lane
+    layout) on the small wet/dry beach, 40 steps against the oracle; the
+    two-part split is held to its own bound."""
+    tol = BF16_TOL if path == "fused_bf16x3" else TOL
+    g, o, q = _compare(f"bf16-N{N}-{path}", W.small_wetdry(n=12, N=N), 40, precision=path, tol=tol,
+                       tol_m=tol, flip_frac=0.01)
+    assert g.diagnostics(0)["min_depth"] >= 0.0
+
+
 @pytest.mark.parametrize("path", ["plain_fp32", "fused_fp32"])
 def test_degree6_vector_alu_paths(path):
     """N = 6 (28 nodes, 21 face nodes) runs only on the vector-ALU kernels
