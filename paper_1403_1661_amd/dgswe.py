@@ -155,6 +155,10 @@ class Solver:
             vx = np.ascontiguousarray(vx, dtype=np.float64)
             vy = np.ascontiguousarray(vy, dtype=np.float64)
             ev = np.ascontiguousarray(etov, dtype=np.int32)
+            if ev.ndim != 2 or ev.shape[1] != 3:
+                raise ValueError(f"mesh {i}: etov must be (K, 3), got {ev.shape}")
+            if vx.shape != vy.shape:
+                raise ValueError(f"mesh {i}: vx and vy differ in shape")
             self._keep += [vx, vy, ev]
             descs[i].n_vertices = vx.size
             descs[i].vx = _dptr(vx)
@@ -163,7 +167,8 @@ class Solver:
             descs[i].etov = ev.ctypes.data_as(C.POINTER(C.c_int32))
             if len(mesh) > 3 and mesh[3] is not None:
                 bc = np.ascontiguousarray(mesh[3], dtype=np.int8)
-                assert bc.shape == ev.shape
+                if bc.shape != ev.shape:
+                    raise ValueError(f"mesh {i}: bc has shape {bc.shape}, etov {ev.shape}")
                 self._keep.append(bc)
                 descs[i].bc = bc.ctypes.data_as(C.POINTER(C.c_int8))
         h = C.c_void_p()
@@ -254,15 +259,22 @@ class Solver:
         return pair, alpha
 
     # -- state ----------------------------------------------------------
+    def _check_nodal(self, inst, a):
+        if not 0 <= inst < self.n_inst:
+            raise IndexError(f"instance {inst} out of range 0..{self.n_inst - 1}")
+        if a.shape != (self.Ks[inst], self.Np):
+            raise ValueError(f"nodal array of instance {inst} must be {(self.Ks[inst], self.Np)}, "
+                             f"got {a.shape}")
+
     def set_bathymetry(self, inst, B):
         B = np.ascontiguousarray(B, dtype=np.float64)
-        assert B.shape == (self.Ks[inst], self.Np)
+        self._check_nodal(inst, B)
         _check(self.lib.dg_set_bathymetry(self.h, inst, _dptr(B)))
 
     def set_state(self, inst, h, hu, hv, stream=None):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (h, hu, hv)]
         for a in arrs:
-            assert a.shape == (self.Ks[inst], self.Np)
+            self._check_nodal(inst, a)
         _check(self.lib.dg_set_state(self.h, inst, *[_dptr(a) for a in arrs],
                                      C.c_void_p(self._stream(stream))))
 

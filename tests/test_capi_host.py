@@ -159,3 +159,24 @@ def test_error_paths():
 
 class _NoStream:
     cuda_stream = 0
+
+
+def test_binding_shape_checks():
+    """The binding rejects malformed arrays before they reach the library."""
+    vx = np.array([0.0, 1.0, 0.0, 1.0])
+    vy = np.array([0.0, 0.0, 1.0, 1.0])
+    with pytest.raises(ValueError):
+        dgswe.Solver([(vx, vy, np.array([0, 1, 2]))], 2)                      # etov not (K, 3)
+    with pytest.raises(ValueError):
+        dgswe.Solver([(vx, vy[:3], np.array([[0, 1, 2]]))], 2)               # vx, vy differ
+    with pytest.raises(ValueError):
+        dgswe.Solver([(vx, vy, np.array([[0, 1, 2]]), np.zeros((1, 2)))], 2)  # bc not (K, 3)
+    s = dgswe.Solver([(vx, vy, np.array([[0, 1, 3], [0, 3, 2]]))], 2)
+    x, _ = s.node_coords(0)
+    with pytest.raises(ValueError):
+        s.set_bathymetry(0, np.zeros((x.shape[0], x.shape[1] - 1)))
+    with pytest.raises(IndexError):
+        s.set_bathymetry(1, np.zeros_like(x))
+    s.set_bathymetry(0, np.zeros_like(x))
+    with pytest.raises(ValueError):
+        s.set_state(0, np.ones_like(x)[:1], 0 * x, 0 * x, stream=_NoStream())
