@@ -128,6 +128,27 @@ def test_multirate_tiny_levels(path):
     assert flag_flips(g.flags(0), o.flags) == (0, 0)
 
 
+@pytest.mark.parametrize("path", ["fused_mfma32", "fused_bf16x6"])
+@pytest.mark.parametrize("N", [1, 2, 4, 5])
+def test_multirate_other_orders(path, N):
+    """Multi-rate AB3 at the orders other than 3: the 16-lane groups (N = 1,
+    2, 4) and the packed 21-lane groups (N = 5) of the multi-rate step kernel,
+    four levels on the small graded band mesh, four coarse steps."""
+    _require_gpu()
+    import dataclasses
+    wl = dataclasses.replace(W.c3(n0=2), N=N)
+    g = gpu_solver(wl, precision=path)
+    o = oracle_solver(wl)
+    lev, _ = g.levels(0)
+    assert np.array_equal(lev.astype(int), o.levels)
+    g.advance(4)
+    o.run(4)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    log(f"[mrab-N{N}] {path} K={wl.n_elements} relL2 h={err['h']:.3e} m={err['m']:.3e}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert flag_flips(g.flags(0), o.flags) == (0, 0)
+
+
 def test_multirate_block_shapes_bitwise():
     """The multi-rate launch cuts each level's element range into whole
     blocks; 1, 2 or 4 waves per block change only that cut, so the MRAB
