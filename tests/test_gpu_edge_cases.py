@@ -128,12 +128,13 @@ def test_multirate_tiny_levels(path):
     assert flag_flips(g.flags(0), o.flags) == (0, 0)
 
 
-@pytest.mark.parametrize("path", ["fused_mfma32", "fused_bf16x6"])
+@pytest.mark.parametrize("path", ["plain_fp32", "fused_fp32", "fused_mfma32", "fused_bf16x6"])
 @pytest.mark.parametrize("N", [1, 2, 4, 5])
 def test_multirate_other_orders(path, N):
-    """Multi-rate AB3 at the orders other than 3: the 16-lane groups (N = 1,
-    2, 4) and the packed 21-lane groups (N = 5) of the multi-rate step kernel,
-    four levels on the small graded band mesh, four coarse steps."""
+    """Multi-rate AB3 at the orders other than 3: the vector-ALU kernels and,
+    on the matrix cores, the 16-lane groups (N = 1, 2, 4) and the packed
+    21-lane groups (N = 5) of the multi-rate step kernel; four levels on the
+    small graded band mesh, four coarse steps."""
     _require_gpu()
     import dataclasses
     wl = dataclasses.replace(W.c3(n0=2), N=N)
