@@ -298,6 +298,32 @@ def test_multirate_graded_bands(path):
     assert pp + tv == 0
 
 
+@pytest.mark.parametrize("N", [1, 3, 5])
+@pytest.mark.parametrize("path", PATHS)
+def test_multirate_wetdry(path, N):
+    """Multi-rate AB3 with both limiters at work: a shoreline through the
+    second-finest level next to dry coarser levels (the graded beach), 10
+    coarse steps = 80 ticks; the positivity limiter scales and dries elements
+    of the active levels at every tick (Algorithm 5.1 applied level by
+    level)."""
+    g, o, q = _compare(f"mrab-wetdry-N{N}", W.graded_beach(N=N), 10, precision=path, flip_frac=0.01)
+    lev, _ = g.levels(0)
+    assert np.array_equal(lev.astype(int), o.levels)
+    d = g.diagnostics(0)
+    assert d["min_depth"] >= 0.0
+    assert d["pp_counts"][1] + d["pp_counts"][2] > 0
+
+
+def test_multirate_wetdry_tvd():
+    """The same case with M = 0 so that the TVB limiter limits on the levels
+    it updates; flips of near-tie keep-or-limit decisions are bounded as in
+    the single-rate TVD test."""
+    g, o, q = _compare("mrab-wetdry-tvd", W.graded_beach(N=3), 10, precision="fused_mfma32",
+                       tvb_M=0.0, flip_frac=0.05, tol=1e-4, tol_m=1e-2)
+    d = g.diagnostics(0)
+    assert d["tvb_counts"][2] + d["tvb_counts"][3] > 0
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_multirate_graph_matches_eager(path):
     _require_gpu()

@@ -330,6 +330,29 @@ def lake_at_rest(n: int = 4, N: int = 3, jitter: float = 0.2, seed: int = 11,
                     cfl=0.5, seed=seed, notes="lake at rest")
 
 
+def graded_beach(n0: int = 2, N: int = 3, n_bands: int = 4) -> Workload:
+    """Multi-rate wet/dry case: the graded band mesh of ``c3`` under a plane
+    beach B = 0.3 (4 - x) whose shoreline (still level 0.55, x ~ 2.17) runs
+    through the second-finest band next to the interface with the coarser
+    bands, which are dry; a hump 0.1 exp(-100 r^2) at (2.3, 0.5) straddles
+    the shoreline.  Walls all round."""
+    vx, vy, etov = graded_band_mesh(n0, n_bands)
+
+    def bath(x, y):
+        return on_bed_grid(0.3 * (float(n_bands) - np.asarray(x, dtype=np.float64)))
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        eta = 0.55 + 0.1 * np.exp(-100.0 * ((x - 2.3) ** 2 + (y - 0.5) ** 2))
+        h = np.maximum(0.0, eta - bath(x, y))
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload("graded_beach", N, [Instance(vx, vy, etov, bath, init, "graded_beach")],
+                    steps=10, cfl=0.3, max_levels=n_bands, seed=0,
+                    notes=f"graded bands n0={n0}, N={N}, B=0.3(4-x), still level 0.55, hump at (2.3, 0.5)")
+
+
 def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Workload:
     """A small beach with a hump straddling the shoreline (exercises both limiters)."""
     rng = np.random.default_rng(seed)
