@@ -339,3 +339,18 @@ def test_wetdry_run_conserves_mass_and_positivity():
     assert abs(s.mass() - m0) / m0 < 1e-12
     pp_tot = sum(fc[0] for fc in s.flag_counts)
     assert pp_tot[1] > 0 and pp_tot[2] > 0
+
+
+def test_mrab_wetdry_positivity_and_mass():
+    """The graded beach with its hump, 10 coarse steps of the multi-rate
+    schedule: depth stays non-negative after every coarse step, no mean goes
+    negative, and mass is conserved to roundoff (walls all round; the dry
+    coarse levels exchange no flux)."""
+    wl = W.graded_beach(N=3)
+    s = make(wl, Params(g=wl.g, cfl=wl.cfl, max_levels=4))
+    m0 = s.mass()
+    for _ in range(10):
+        s.run(1)
+        assert np.all(s.q[0] >= 0.0) and np.all(np.isfinite(s.q))
+    assert abs(s.mass() - m0) / m0 < 1e-12
+    assert s.flags.pp.max() == PP_DRY
