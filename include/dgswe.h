@@ -230,8 +230,13 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
 
 /* Checkpoint: the full time-stepping state (states, RHS history, half-step
  * traces, counters) as an opaque byte blob; dg_checkpoint_bytes gives the
- * size.  Restoring onto a solver created with the same meshes and params
- * continues bit-identically.  Both synchronise `stream`. */
+ * size (a header with every instance's simulated time, then the device
+ * state; any number of instances).  Restoring onto a solver created with the
+ * same meshes and params continues bit-identically, single-rate or
+ * multi-rate.  Both synchronise `stream`.  Errors: DG_EINVAL for a buffer
+ * shorter than dg_checkpoint_bytes or a blob of another solver shape (K, Np,
+ * levels, instances); dg_get_checkpoint DG_ENOTBOUND before any state is on
+ * the device; dg_set_checkpoint DG_ESTATE before dg_prepare or dg_advance. */
 int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes);
 int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream);
 int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* stream);

@@ -48,7 +48,7 @@ struct Inst {
     HostMesh mesh;
     int offset = 0;          // first global (unsorted) element index
     bool has_B = false, has_state = false;
-    double dt_min = 0.0, a_max = 0.0, time = 0.0;
+    double dt_min = 0.0, a_max = 0.0;
     // Vertical datum of the instance: the device stores eta - datum and
     // B - datum in FP32.  Every formula of the scheme depends on depths and
     // surface-level differences only, so the shift changes nothing but the
@@ -76,7 +76,8 @@ struct dg_solver {
     std::vector<int> conn;
     // time stepping state
     int parity[kMaxLevels] = {0}, head[kMaxLevels] = {0}, nhist[kMaxLevels] = {0};
-    long long steps = 0;
+    long long steps = 0;     // coarse steps since dg_prepare
+    int64_t ticks = 0;       // finest-level ticks since dg_prepare (simulated time = ticks * dt_min)
     // execution
     hipStream_t exec = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -638,7 +639,6 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
     for (double r : I.mesh.inradius) rmin = std::fmin(rmin, r);
     I.a_max = amax;
     I.dt_min = h->p.cfl * rmin / (double((h->p.N + 1) * (h->p.N + 1)) * std::fmax(amax, 1e-12));
-    I.time = 0.0;
     I.has_state = true;
     h->prepared = false;
     return DG_OK;
@@ -796,8 +796,7 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
             h->nhist[l] = std::min(h->nhist[l] + 1, 2);
         }
     }
-    if (!limit_only)
-        for (size_t i = 0; i < h->inst.size(); ++i) h->inst[i].time += h->inst[i].dt_min;
+    if (!limit_only) ++h->ticks;
     return DG_OK;
 }
 
@@ -850,7 +849,7 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
     HIPCHECK(hipMemcpyAsync(h->ws + l.Q[0] + 12 * h->Ql.size(), h->Ql.data(), h->Ql.size() * 2,
                             hipMemcpyHostToDevice, s));
     h->steps = 0;
-    for (auto& I : h->inst) I.time = 0.0;
+    h->ticks = 0;
     // Q0 = TVB(PP(Pi_H Q0)), first line of Algorithm 5.1
     const int rc = enqueue_tick(h, 0, s, true);
     if (rc) return rc;
@@ -901,7 +900,7 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
                 h->have_graph = true;
                 // capture advanced the host-side counters; undo them, the launch below replays
                 h->steps -= period;
-                for (auto& I : h->inst) I.time -= period * (1 << (h->L - 1)) * I.dt_min;
+                h->ticks -= int64_t(period) << (h->L - 1);
             }
             hipEvent_t e0, e1;
             HIPCHECK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
@@ -912,7 +911,7 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
                 HIPCHECK(hipGraphLaunch(h->graph, h->exec));
                 n_steps -= period;
                 h->steps += period;
-                for (auto& I : h->inst) I.time += period * (1 << (h->L - 1)) * I.dt_min;
+                h->ticks += int64_t(period) << (h->L - 1);
             }
             HIPCHECK(hipEventRecord(e1, h->exec));
             HIPCHECK(hipStreamWaitEvent(s, e1, 0));
@@ -1081,7 +1080,9 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
     HIPCHECK(hipMemcpy(cnt, h->ws + l.counters, 8, hipMemcpyDeviceToHost));
     d->mass = out[0];
     d->min_depth = out[1];
-    d->time = h->inst[inst].time;
+    // simulated time from the tick count: independent of how the ticks were
+    // grouped into launches, graph replays or checkpointed runs
+    d->time = double(h->ticks) * h->inst[inst].dt_min;
     d->steps = h->steps;
     d->negative_means = (int64_t)cnt[0];
     for (int q = 0; q < 3; ++q) d->pp_counts[q] = (int64_t)out[2 + q];
@@ -1089,41 +1090,46 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
     return DG_OK;
 }
 
+// checkpoint blob: a 256-byte header (solver shape, per-level schedule
+// state, step and tick counts), then the device state
+static size_t ckpt_header_bytes(const dg_solver*) { return 256; }
+
 int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes) {
     if (!h || !bytes) return fail(DG_EINVAL, "bad argument");
-    *bytes = int64_t(256 + (h->lay.dyn_end - h->lay.dyn_begin));
+    *bytes = int64_t(ckpt_header_bytes(h) + (h->lay.dyn_end - h->lay.dyn_begin));
     return DG_OK;
 }
 
 struct CkptHeader {
-    uint64_t magic, K, Np, L;
+    uint64_t magic, K, Np, L, n_inst;
     int32_t parity[kMaxLevels], head[kMaxLevels], nhist[kMaxLevels];
-    int64_t steps;
+    int64_t steps, ticks;
 };
+static_assert(sizeof(CkptHeader) <= 256, "checkpoint header exceeds its slot");
 
 int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream) {
     int64_t need = 0;
     if (dg_checkpoint_bytes(h, &need)) return DG_EINVAL;
     if (!blob || bytes < need) return fail(DG_EINVAL, "checkpoint buffer too small");
     if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
-    if (h->inst.size() > 8) return fail(DG_EINVAL, "checkpoints support at most 8 instances");
     HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     char* b = static_cast<char*>(blob);
-    std::memset(b, 0, 256);
+    const size_t hb = ckpt_header_bytes(h);
+    std::memset(b, 0, hb);
     CkptHeader* hd = reinterpret_cast<CkptHeader*>(b);
     hd->magic = 0x44475357u;
     hd->K = h->K;
     hd->Np = h->Np;
     hd->L = h->L;
+    hd->n_inst = h->inst.size();
     for (int l = 0; l < kMaxLevels; ++l) {
         hd->parity[l] = h->parity[l];
         hd->head[l] = h->head[l];
         hd->nhist[l] = h->nhist[l];
     }
     hd->steps = h->steps;
-    double* times = reinterpret_cast<double*>(b + 128);
-    for (size_t i = 0; i < h->inst.size(); ++i) times[i] = h->inst[i].time;
-    HIPCHECK(hipMemcpy(b + 256, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
+    hd->ticks = h->ticks;
+    HIPCHECK(hipMemcpy(b + hb, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
                        hipMemcpyDeviceToHost));
     return DG_OK;
 }
@@ -1136,10 +1142,10 @@ int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* s
     const char* b = static_cast<const char*>(blob);
     const CkptHeader* hd = reinterpret_cast<const CkptHeader*>(b);
     if (hd->magic != 0x44475357u || hd->K != uint64_t(h->K) || hd->Np != uint64_t(h->Np) ||
-        hd->L != uint64_t(h->L))
+        hd->L != uint64_t(h->L) || hd->n_inst != uint64_t(h->inst.size()))
         return fail(DG_EINVAL, "checkpoint does not match this solver");
     HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-    HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + 256, h->lay.dyn_end - h->lay.dyn_begin,
+    HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + ckpt_header_bytes(h), h->lay.dyn_end - h->lay.dyn_begin,
                        hipMemcpyHostToDevice));
     for (int l = 0; l < kMaxLevels; ++l) {
         h->parity[l] = hd->parity[l];
@@ -1147,8 +1153,7 @@ int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* s
         h->nhist[l] = hd->nhist[l];
     }
     h->steps = hd->steps;
-    const double* times = reinterpret_cast<const double*>(b + 128);
-    for (size_t i = 0; i < h->inst.size(); ++i) h->inst[i].time = times[i];
+    h->ticks = hd->ticks;
     return DG_OK;
 }
 

@@ -179,6 +179,31 @@ def test_checkpoint_resume_and_determinism():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("case", ["multirate", "ensemble12"])
+def test_checkpoint_resume_multirate_and_ensemble(case):
+    """Checkpoints of the multi-rate schedule (per-level history, parity and
+    half-step traces, taken between coarse steps) and of an ensemble of more
+    instances than fit one header slot resume bit-identically."""
+    _require_gpu()
+    wl = W.graded_beach(N=3) if case == "multirate" else W.c5(n_inst=12, kmin=50, kmax=300)
+    n = 3 if case == "multirate" else 20
+    log(f"[checkpoint-{case}] K={wl.n_elements}")
+    a = gpu_solver(wl, precision="fused_mfma32")
+    a.advance(n)
+    blob = a.checkpoint()
+    a.advance(n)
+    b = gpu_solver(wl, precision="fused_mfma32")
+    b.prepare()
+    b.restore(blob)
+    b.advance(n)
+    for i in range(len(wl.instances)):
+        for x, y in zip(a.get_state(i), b.get_state(i)):
+            assert np.array_equal(x, y)
+        _, dt = a.levels(i)
+        ticks = 2 * n * 2 ** (wl.max_levels - 1)
+        assert a.diagnostics(i)["time"] == b.diagnostics(i)["time"] == float(ticks) * dt
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_ensemble_matches_single_instances(path):
     _require_gpu()
