@@ -150,6 +150,28 @@ def test_multirate_other_orders(path, N):
     assert flag_flips(g.flags(0), o.flags) == (0, 0)
 
 
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_tvb_fallback_stencil(path, N):
+    """TVB limiting through the one-neighbour fallback of the stencil (two
+    edges of the central element of the skewed patch) and next to a sliver:
+    M = 0, every element limited at every step, 10 steps."""
+    _require_gpu()
+    wl = W.skewed_patch(N=N)
+    g = gpu_solver(wl, precision=path, tvb_M=0.0)
+    o = oracle_solver(wl, tvb_M=0.0)
+    pair, _ = g.tvb_stencil(0)
+    assert pair[0, 0, 0] == pair[0, 0, 1] and pair[0, 2, 0] == pair[0, 2, 1]
+    g.advance(10)
+    o.run(10)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    log(f"[tvb-fallback] N={N} {path} relL2 h={err['h']:.3e} m={err['m']:.3e} "
+        f"flags {g.flags(0).tolist()}")
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    assert flag_flips(g.flags(0), o.flags) == (0, 0)
+    assert np.all((o.flags.tvb == 2) | (o.flags.tvb == 3))
+
+
 def test_multirate_block_shapes_bitwise():
     """The multi-rate launch cuts each level's element range into whole
     blocks; 1, 2 or 4 waves per block change only that cut, so the MRAB

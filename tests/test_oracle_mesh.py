@@ -152,3 +152,32 @@ def test_tvb_stencil_reconstructs_linear_functions():
         assert np.allclose(np.linalg.norm(st.direction[:, i], axis=1), 1.0)
     # most interior edges find a valid pair on a jittered mesh
     assert np.mean(st.pair[interior, :, 0] != st.pair[interior, :, 1]) > 0.9
+
+
+def test_tvb_stencil_fallback_on_skewed_neighbourhood():
+    """Where the neighbour barycentres do not surround the element's own, no
+    pair of them spans the direction to an edge midpoint with non-negative
+    weights; that edge falls back to its face neighbour alone, with the weight
+    that gives the neighbour direction the length of the midpoint offset."""
+    wl = W.skewed_patch(N=2)
+    ins = wl.instances[0]
+    m = build_mesh(ins.vx, ins.vy, ins.etov, reference_element(2))
+    st = tvb_stencil(m)
+    px, py = m.vx[m.etov], m.vy[m.etov]
+    b0 = np.stack([px.mean(1), py.mean(1)], 1)
+    mid = np.stack([0.5 * (px + np.roll(px, -1, 1)), 0.5 * (py + np.roll(py, -1, 1))], 2)
+    fb = st.pair[:, :, 0] == st.pair[:, :, 1]
+    assert fb[0].tolist() == [True, False, True]
+    for i in (0, 2):
+        # no pair spans the offset with non-negative weights
+        d = mid[0, i] - b0[0]
+        nb = b0[m.etoe[0]] - b0[0]
+        for j, k in ((0, 1), (0, 2), (1, 2)):
+            w = np.linalg.solve(np.stack([nb[j], nb[k]], 1), d)
+            assert w.min() < 0
+        assert st.alpha[0, i, 1] == 0.0
+        assert abs(st.alpha[0, i, 0] * np.linalg.norm(nb[i]) - np.linalg.norm(d)) < 1e-14
+    # the middle edge spans exactly
+    rec = st.alpha[0, 1, 0] * (b0[m.etoe[0, st.pair[0, 1, 0]]] - b0[0]) + \
+        st.alpha[0, 1, 1] * (b0[m.etoe[0, st.pair[0, 1, 1]]] - b0[0])
+    assert np.max(np.abs(rec - (mid[0, 1] - b0[0]))) < 1e-14

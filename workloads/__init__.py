@@ -353,6 +353,29 @@ def graded_beach(n0: int = 2, N: int = 3, n_bands: int = 4) -> Workload:
                     notes=f"graded bands n0={n0}, N={N}, B=0.3(4-x), still level 0.55, hump at (2.3, 0.5)")
 
 
+def skewed_patch(N: int = 2) -> Workload:
+    """Four triangles around a flat central one whose neighbour barycentres do
+    not surround its own: two of its edges find no neighbour pair with
+    non-negative weights and take the one-neighbour fallback of the TVB
+    stencil.  One neighbour is a sliver.  Flat bed, walls all round, a depth
+    step at x = 0.6 plus a slope in y (every element is limited)."""
+    vx = np.array([0.0, 1.0, 0.5, 3.0, 1.2, -0.2])
+    vy = np.array([0.0, 0.0, 0.3, -0.05, 0.5, 0.5])
+    etov = np.array([[0, 1, 2], [0, 3, 1], [1, 4, 2], [2, 5, 0]], dtype=np.int64)
+
+    def bath(x, y):
+        return _zeros_like(np.asarray(x, dtype=np.float64))
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        h = 1.0 + 0.3 * (x > 0.6) + 0.2 * y
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload("skewed_patch", N, [Instance(vx, vy, etov, bath, init, "skewed_patch")],
+                    steps=10, cfl=0.3, notes="TVB stencil fallback case")
+
+
 def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Workload:
     """A small beach with a hump straddling the shoreline (exercises both limiters)."""
     rng = np.random.default_rng(seed)
