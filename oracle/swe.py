@@ -236,7 +236,14 @@ class Solver:
         K = q.shape[1]
         code = np.zeros(K, dtype=np.uint8)
         hmin = q[0].min(axis=1)
-        trig = hmin <= p.eps
+        # Algorithm 5.2 keeps an element whose nodal depths all exceed eps.
+        # At orders 4 and 6 three vertex weights of the nodal mean are
+        # negative, so such an element can still have a mean below h0, even
+        # a negative one, which the TVB stage cannot take (its wave speed is
+        # sqrt(g hbar)); these elements take the rest of Algorithm 5.2 too
+        # (the dry branch, since hbar < h0).  With positive weights and
+        # eps <= h0 this adds nothing.
+        trig = (hmin <= p.eps) | (self.means(q)[0] < p.h0)
         if active is not None:
             trig &= active
         neg = 0

@@ -425,7 +425,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         double scale = 1.0;
         int code = 0;
         double hdry = 0.0;
-        if (a.pp_on && hmin <= (double)a.eps) {
+        // a mean below h0 with every node above eps (negative vertex weights
+        // of the nodal mean at N = 4, 6) also takes the dry branch
+        if (a.pp_on && (hmin <= (double)a.eps || hb < (double)a.h0)) {
             if (hb < (double)a.h0) {
                 code = 2;
                 if (hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
@@ -1114,7 +1116,9 @@ step_mfma_kernel(StepArgs a) {
     const double hb = sRed[q][1];
     double scale = 1.0, hdry = 0.0;
     int code = 0;
-    if (a.pp_on && hmin <= (double)a.eps) {
+    // a mean below h0 with every node above eps (negative vertex weights of
+    // the nodal mean at N = 4, 6) also takes the dry branch
+    if (a.pp_on && (hmin <= (double)a.eps || hb < (double)a.h0)) {
         if (hb < (double)a.h0) {
             code = 2;
             hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);

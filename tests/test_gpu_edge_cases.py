@@ -172,6 +172,36 @@ def test_tvb_fallback_stencil(path, N):
     assert np.all((o.flags.tvb == 2) | (o.flags.tvb == 3))
 
 
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_near_dry_front(path, N):
+    """Deep water against a thin film with M = 0 and h0 = 1e-3: the depth
+    modification of Eq. 5.3 on limited elements next to the film, and at
+    N = 4 elements whose nodes are all wet but whose mean is negative (made
+    dry by the positivity limiter).  The initial limiting and 5 steps."""
+    _require_gpu()
+    wl = W.near_dry_front(N=N)
+    g = gpu_solver(wl, precision=path, tvb_M=0.0, h0=1e-3)
+    o = oracle_solver(wl, tvb_M=0.0, h0=1e-3)
+    g.prepare()
+    err0 = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    flips0 = flag_flips(g.flags(0), o.flags)
+    tv_o = np.bincount(o.flags.tvb, minlength=4)
+    g.advance(5)
+    o.run(5)
+    err = rel_l2(o, np.stack(g.get_state(0)), o.q)
+    flips = flag_flips(g.flags(0), o.flags)
+    log(f"[near-dry] N={N} {path} initial relL2 h={err0['h']:.3e} m={err0['m']:.3e} flips {flips0} "
+        f"tvb codes {tv_o.tolist()}; 5 steps relL2 h={err['h']:.3e} m={err['m']:.3e} flips {flips}")
+    assert tv_o[3] > 0 or N == 1
+    assert err0["h"] <= 1e-5 and err0["m"] <= 1e-5 and flips0 == (0, 0)
+    assert err["h"] <= 1e-5 and err["m"] <= 1e-5
+    # M = 0 compares nearly equal characteristic increments: FP32 and FP64
+    # part on a few keep-or-limit decisions (as in the TVD test of C1)
+    assert sum(flips) <= 0.05 * wl.n_elements
+    assert g.diagnostics(0)["min_depth"] >= 0.0
+
+
 def test_multirate_block_shapes_bitwise():
     """The multi-rate launch cuts each level's element range into whole
     blocks; 1, 2 or 4 waves per block change only that cut, so the MRAB

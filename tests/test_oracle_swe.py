@@ -354,3 +354,42 @@ def test_mrab_wetdry_positivity_and_mass():
         assert np.all(s.q[0] >= 0.0) and np.all(np.isfinite(s.q))
     assert abs(s.mass() - m0) / m0 < 1e-12
     assert s.flags.pp.max() == PP_DRY
+
+
+def test_pp_negative_mean_with_wet_nodes_is_dry():
+    """At N = 4 the nodal mean weights of the three vertices are negative, so
+    an element wet at its vertices and nearly dry elsewhere has every node
+    above eps and a negative mean (checked here through the constant modal
+    coefficient, not the nodal weights).  The limiter makes it dry instead of
+    keeping it."""
+    wl = W.lake_at_rest(n=3, N=4)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 4, Params())
+    ref = s.ref
+    assert np.sum(ref.w < 0) == 3
+    h = np.full((s.K, ref.Np), 1e-4)
+    vert = [int(np.argmin((ref.r - a) ** 2 + (ref.s - b) ** 2)) for a, b in ((-1, -1), (1, -1), (-1, 1))]
+    h[0, vert] = 1.0
+    mean_modal = np.linalg.solve(ref.V, h[0])[0] / np.sqrt(2.0)
+    assert mean_modal < 0.0 and h[0].min() > s.p.eps
+    q = np.stack([h, 0.1 * h, -0.1 * h])
+    out, code, neg = s.pp_limit(q)
+    assert code[0] == PP_DRY and neg == 1
+    assert np.all(out[:, 0] == 0.0)
+    assert np.all(code[1:] == PP_KEEP)
+
+
+def test_near_dry_front_stays_finite_at_order_4():
+    """The deep-water / thin-film front at N = 4 with M = 0: without the
+    negative-mean rule above, the limiter's characteristic speed of such an
+    element is the square root of a negative mean and the run fails in its
+    first step."""
+    wl = W.near_dry_front(N=4)
+    s = make(wl, Params(cfl=wl.cfl, tvb_M=0.0, h0=1e-3))
+    m0 = s.mass()
+    for _ in range(5):
+        s.step()
+        assert np.all(np.isfinite(s.q)) and np.all(s.q[0] >= 0.0)
+    tv = sum(fc[1] for fc in s.flag_counts)
+    assert tv[3] > 0   # Eq. 5.3 at work
+    assert abs(s.mass() - m0) / m0 < 1e-3

@@ -376,6 +376,28 @@ def skewed_patch(N: int = 2) -> Workload:
                     steps=10, cfl=0.3, notes="TVB stencil fallback case")
 
 
+def near_dry_front(N: int = 3, n: int = 8, seed: int = 7) -> Workload:
+    """A depth front between deep water (h = 1) and a thin film (h ~ 0.002)
+    along x + 0.3 y = 0.55 on a jittered n x n x 2 unit square, flat bed,
+    momentum (0.3 h sin 3y, 0.1 h): run with M = 0 and h0 = 1e-3, limited
+    elements next to the film take the depth modification of Eq. 5.3, and at
+    N = 4 some elements with every node wet have a negative mean."""
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=0.2, rng=rng)
+
+    def bath(x, y):
+        return _zeros_like(np.asarray(x, dtype=np.float64))
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        h = np.where(x + 0.3 * y < 0.55, 1.0, 0.002) + 0.001 * x * (0.5 + 0.5 * np.sin(17.0 * x + 5.0 * y))
+        return h, 0.3 * h * np.sin(3.0 * y), 0.1 * h
+
+    return Workload("near_dry_front", N, [Instance(vx, vy, etov, bath, init, "near_dry_front")],
+                    steps=5, cfl=0.2, seed=seed, notes="deep water against a thin film")
+
+
 def small_wetdry(n: int = 8, N: int = 3, seed: int = 12, steps: int = 40) -> Workload:
     """A small beach with a hump straddling the shoreline (exercises both limiters)."""
     rng = np.random.default_rng(seed)
