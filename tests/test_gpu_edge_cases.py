@@ -172,8 +172,8 @@ def test_tvb_fallback_stencil(path, N):
     assert np.all((o.flags.tvb == 2) | (o.flags.tvb == 3))
 
 
-@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
-@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("N,path", [(N, p) for N in (1, 2, 3, 4, 5) for p in ("fused_fp32", "fused_mfma32")]
+                         + [(6, "fused_fp32")])
 def test_near_dry_front(path, N):
     """Deep water against a thin film with M = 0 and h0 = 1e-3: the depth
     modification of Eq. 5.3 on limited elements next to the film, and at
