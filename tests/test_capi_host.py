@@ -183,3 +183,15 @@ def test_binding_shape_checks():
     s.set_bathymetry(0, np.zeros_like(x))
     with pytest.raises(ValueError):
         s.set_state(0, np.ones_like(x)[:1], 0 * x, 0 * x, stream=_NoStream())
+
+
+def test_non_finite_bathymetry_rejected():
+    vx = np.array([0.0, 1.0, 0.0, 1.0])
+    vy = np.array([0.0, 0.0, 1.0, 1.0])
+    s = dgswe.Solver([(vx, vy, np.array([[0, 1, 3], [0, 3, 2]]))], 2)
+    x, _ = s.node_coords(0)
+    B = np.zeros_like(x)
+    B[1, 2] = np.nan
+    with pytest.raises(dgswe.DGError) as e:
+        s.set_bathymetry(0, B)
+    assert e.value.code == -6
