@@ -85,6 +85,50 @@ class StepFlags:
     neg_mean: int = 0
 
 
+def char_left(ub, vb, c, ex, ey):
+    """Rows of the left eigenvectors L of the flux Jacobian A = F'(q) ex +
+    G'(q) ey of Eq. 2.2 in direction (ex, ey) (unit), at the state with
+    velocity (ub, vb) and celerity c = sqrt(g h): L A R = diag(un - c, un,
+    un + c) with un = ub ex + vb ey.  Arrays of n states -> (n, 3, 3)."""
+    un = ub * ex + vb * ey
+    ut = -ub * ey + vb * ex
+    return np.stack([
+        np.stack([(un + c) / (2 * c), -ex / (2 * c), -ey / (2 * c)], axis=-1),
+        np.stack([-ut, -ey, ex], axis=-1),
+        np.stack([-(un - c) / (2 * c), ex / (2 * c), ey / (2 * c)], axis=-1)], axis=1)
+
+
+def char_right(ub, vb, c, ex, ey):
+    """Right eigenvectors R (columns) of the same Jacobian, R = L^-1:
+    acoustic waves (1, ub -+ c ex, vb -+ c ey) and the shear wave
+    (0, -ey, ex).  Arrays of n states -> (n, 3, 3)."""
+    one = np.ones_like(ub * ex)
+    return np.stack([
+        np.stack([one, np.zeros_like(one), one], axis=-1),
+        np.stack([ub - c * ex, -ey * one, ub + c * ex], axis=-1),
+        np.stack([vb - c * ey, ex * one, vb + c * ey], axis=-1)], axis=1)
+
+
+def char_minmod(ub, vb, c, ex, ey, dev, dbar, nu, M2):
+    """One edge of the characteristic TVB limiter (Section 5.3, after Cockburn
+    and Shu): the P1 deviation dev (3, n) of the conserved variables at the
+    edge midpoint and the neighbour-mean increment dbar (3, n) go to
+    characteristic variables a1 = L dev, a2 = nu L dbar; each component keeps
+    a1 when |a1| <= M2 (the TVB bypass, M d_K^2) and otherwise takes
+    minmod(a1, a2); the result goes back through R.  Returns the limited
+    deviation (3, n) and whether every component kept a1."""
+    L = char_left(ub, vb, c, ex, ey)
+    Rm = char_right(ub, vb, c, ex, ey)
+    a1 = np.einsum("nab,bn->an", L, dev)
+    a2 = nu * np.einsum("nab,bn->an", L, dbar)
+    small = np.abs(a1) <= M2[None, :]
+    same = np.sign(a1) == np.sign(a2)
+    mm = np.where(same, np.sign(a1) * np.minimum(np.abs(a1), np.abs(a2)), 0.0)
+    mt = np.where(small, a1, mm)
+    ret = small | (a1 == 0.0) | (same & (np.abs(a1) <= np.abs(a2)))
+    return np.einsum("nab,bn->an", Rm, mt), ret.all(axis=0)
+
+
 class Solver:
     """FP64 DG-SWE solver on one triangulation."""
 
@@ -314,25 +358,8 @@ class Solver:
             pk = st.pair[idx, i, 1]
             dbar = st.alpha[idx, i, 0] * diff[:, ar, pj] + st.alpha[idx, i, 1] * diff[:, ar, pk]
             ex, ey = st.direction[idx, i, 0], st.direction[idx, i, 1]
-            un = ub * ex + vb * ey
-            ut = -ub * ey + vb * ex
-            L = np.stack([
-                np.stack([(un + c) / (2 * c), -ex / (2 * c), -ey / (2 * c)], axis=-1),
-                np.stack([-ut, -ey, ex], axis=-1),
-                np.stack([-(un - c) / (2 * c), ex / (2 * c), ey / (2 * c)], axis=-1)], axis=1)
-            Rm = np.stack([
-                np.stack([np.ones(n), np.zeros(n), np.ones(n)], axis=-1),
-                np.stack([ub - c * ex, -ey, ub + c * ex], axis=-1),
-                np.stack([vb - c * ey, ex, vb + c * ey], axis=-1)], axis=1)
-            a1 = np.einsum("nab,bn->an", L, dev[:, :, i])
-            a2 = p.tvb_nu * np.einsum("nab,bn->an", L, dbar)
-            small = np.abs(a1) <= M2[None, :]
-            same = np.sign(a1) == np.sign(a2)
-            mm = np.where(same, np.sign(a1) * np.minimum(np.abs(a1), np.abs(a2)), 0.0)
-            mt = np.where(small, a1, mm)
-            ret = small | (a1 == 0.0) | (same & (np.abs(a1) <= np.abs(a2)))
-            all_a1 &= ret.all(axis=0)
-            delta[:, :, i] = np.einsum("nab,bn->an", Rm, mt)
+            delta[:, :, i], ret = char_minmod(ub, vb, c, ex, ey, dev[:, :, i], dbar, p.tvb_nu, M2)
+            all_a1 &= ret
         code_a = np.full(n, TVB_KEPT, dtype=np.uint8)
         lim = ~all_a1
         if np.any(lim):

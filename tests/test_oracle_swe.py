@@ -208,32 +208,64 @@ def test_mrab_one_level_is_ab3_bitwise():
     assert np.array_equal(a.q, b.q)
 
 
-def test_mrab_two_levels_converges():
-    """Two-level multi-rate AB3 converges to the single-rate solution as
-    dt_min shrinks (order >= 2 including the FE/AB2 start)."""
+def test_mrab_two_levels_third_order():
+    """Two-level multi-rate AB3 (Section 4, Algorithm 4.1, on the tick
+    schedule) converges at third order in dt_min.  The run starts from an
+    exact history (the right-hand sides of a fine RK4 reference at the
+    earlier step times of each level), so the forward Euler / AB2 start-up
+    does not set the order; a wrong half-step weight of the coarse level's
+    interpolant drops the ratio to about 2."""
     wl = W.c3(n0=2, n_bands=2)
     ins = wl.instances[0]
 
-    def run(dt, levels, T):
+    def make_mr(levels):
         s = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=0.3, max_levels=levels,
                                                       pp=False, tvb=False))
         x, y = s.nodes()
-        s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry))
-        s.dt_min = dt
-        n = int(round(T / (dt * 2 ** (levels - 1))))
-        s.run(n)
-        assert np.unique(s.levels).size == levels
-        return s.q
+        s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry), limit=False)
+        return s
 
-    s0 = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=0.3, max_levels=2))
-    x, y = s0.nodes()
-    s0.set_state(*ins.initial(x, y), s0.interpolate(ins.bathymetry))
-    dt0 = s0.dt_min
-    T = 32 * dt0
-    ref = run(dt0 / 16, 1, T)
-    e1 = np.max(np.abs(run(dt0, 2, T) - ref))
-    e2 = np.max(np.abs(run(dt0 / 2, 2, T) - ref))
-    assert e1 / e2 > 3.5, (e1, e2)
+    s0 = make_mr(2)
+    assert np.unique(s0.levels).size == 2
+    dt0, B = s0.dt_min, s0.B
+    hq, T0, T, sub = dt0 / 4, 4 * dt0, 16 * dt0, 16
+
+    def rk4(q, h):
+        k1 = s0.rhs(q, B)
+        k2 = s0.rhs(q + 0.5 * h * k1, B)
+        k3 = s0.rhs(q + 0.5 * h * k2, B)
+        k4 = s0.rhs(q + h * k3, B)
+        return q + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+
+    # reference states every dt0/4 from t = -T0 to T
+    q = s0.q.copy()
+    ref = []
+    n_total = int(round((T0 + T) / hq))
+    for i in range(n_total + 1):
+        ref.append(q.copy())
+        if i < n_total:
+            for _ in range(sub):
+                q = rk4(q, hq / sub)
+
+    def at(t):
+        return ref[int(round((t + T0) / hq))]
+
+    errs = []
+    for dt in (dt0, dt0 / 2, dt0 / 4):
+        s = make_mr(2)
+        s.dt_min = dt
+        s.q = at(0.0).copy()
+        hist = [[] for _ in range(3)]
+        for l in (1, 2):
+            dtl = dt * 2 ** (l - 1)
+            sel = s.levels == l
+            hist[l] = [s.rhs(at(-dtl), B)[:, sel, :], s.rhs(at(-2 * dtl), B)[:, sel, :]]
+        s._mr = {"hist": hist, "half": s.q.copy(), "tick": 0}
+        s.run(int(round(T / (2 * dt))))
+        errs.append(np.max(np.abs(s.q - at(T))))
+    errs = np.array(errs)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios > 6.5), (errs, ratios)
 
 
 # --------------------------------------------------------------- limiters
