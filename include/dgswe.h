@@ -230,27 +230,50 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
 
 /* Checkpoint: the full time-stepping state (states, RHS history, half-step
  * traces, counters) as an opaque byte blob; dg_checkpoint_bytes gives the
- * size (a header with every instance's simulated time, then the device
- * state; any number of instances).  Restoring onto a solver created with the
- * same meshes and params continues bit-identically, single-rate or
- * multi-rate.  Both synchronise `stream`.  Errors: DG_EINVAL for a buffer
- * shorter than dg_checkpoint_bytes or a blob of another solver shape (K, Np,
- * levels, instances); dg_get_checkpoint DG_ENOTBOUND before any state is on
- * the device; dg_set_checkpoint DG_ESTATE before dg_prepare or dg_advance. */
+ * size: a 256-byte header (solver shape, the multi-rate schedule state, the
+ * step and finest-level tick counts), one 32-byte record per instance (the
+ * vertical datum its stored levels are relative to, its time step, its
+ * initial wave-speed bound and a hash of its FP64 bathymetry), then the
+ * device state; any number of instances.  Restoring onto a solver created
+ * with the same meshes, params and bathymetry continues bit-identically,
+ * single-rate or multi-rate, whatever state dg_set_state staged on it: the
+ * restore takes the datum and time step of every instance from the blob
+ * (rebuilding the shifted bed on the device), so each instance's simulated
+ * time is the tick count times the restored time step.  A later dg_prepare
+ * returns to the staged state.  Both synchronise `stream`.  Errors:
+ * DG_EINVAL for a buffer shorter than dg_checkpoint_bytes, a blob of another
+ * solver shape (K, Np, levels, instances) or bathymetry, or a corrupt blob
+ * (schedule state outside its ranges, negative counts, a non-finite or
+ * non-positive instance record), each detected before anything is copied;
+ * dg_get_checkpoint DG_ENOTBOUND before any state is on the device;
+ * dg_set_checkpoint DG_ESTATE before dg_prepare or dg_advance. */
 int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes);
 int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream);
 int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* stream);
 
-/* Device timing of the step kernel.  dg_set_profiling(h, 1) starts a timed
- * region (and resets it): every later step-kernel launch of dg_advance runs
- * eagerly with start/stop events stamped by its dispatch, on the stream it
- * runs on.  dg_kernel_timing returns the average duration in microseconds,
- * the number of timed launches and the average number of elements per timed
- * launch (all elements single rate; the active levels of each tick with
- * multi-rate stepping).  Synchronises on the recorded events. */
+/* Device timing of the step and TVB kernels.  dg_set_profiling(h, 1) starts
+ * a timed region (and resets it): every later tick of dg_advance runs eagerly
+ * with start/stop events stamped by the dispatch of its step kernel and of
+ * its TVB kernel, on the stream they run on.  dg_kernel_timing(h, which, ...)
+ * returns, for which = 0 (step kernel) or 1 (TVB kernel), the average
+ * duration in microseconds and the number of timed launches, and the average
+ * number of elements per timed launch (all elements single rate; the active
+ * levels of each tick with multi-rate stepping; the TVB kernel of a tick
+ * covers the same range).  Synchronises on the recorded events.  Errors:
+ * DG_EINVAL (null handle, unknown kernel id), DG_EDEVICE. */
 int32_t dg_set_profiling(dg_solver* h, int32_t on);
-int32_t dg_kernel_timing(const dg_solver* h, double* avg_us, int64_t* launches,
+int32_t dg_kernel_timing(const dg_solver* h, int32_t which, double* avg_us, int64_t* launches,
                          int64_t* elements_per_launch);
+
+/* Capture the replay graph of dg_advance now, from the current schedule
+ * state, without running any step: the next six coarse steps (the period of
+ * the RHS ring and the state ping-pong) are recorded on the library's stream
+ * and instantiated, so that a later dg_advance of six or more steps from the
+ * same schedule position replays them without paying for capture.  Needs the
+ * Adams-Bashforth start-up to be over (two steps advanced since dg_prepare)
+ * and use_graph = 1.  Synchronises `stream`.  Errors: DG_EINVAL (null
+ * handle), DG_ESTATE (start-up not over, graphs off), DG_EDEVICE. */
+int32_t dg_capture_graph(dg_solver* h, void* stream);
 
 #ifdef __cplusplus
 }

@@ -38,7 +38,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t Q[2], R[3], half, mrec, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
-    size_t B, dB, geo, conn, stencil;
+    size_t B, Blo, dB, geo, conn, stencil;
     size_t Dr, Ds, LIFT, Amfma, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
     size_t diag_partial, diag_out;
     size_t total;
@@ -54,6 +54,10 @@ struct Inst {
     // surface-level differences only, so the shift changes nothing but the
     // FP32 rounding of the stored surface level, which shrinks with |eta - datum|.
     float datum = 0.f;
+    // datum, time step and wave speed of the state staged by dg_set_state
+    // (dg_prepare starts from them; a restored checkpoint brings its own)
+    float staged_datum = 0.f;
+    double staged_dt_min = 0.0, staged_a_max = 0.0;
 };
 
 }  // namespace
@@ -72,6 +76,7 @@ struct dg_solver {
     // host staging (sorted order, FP32)
     std::vector<float> geo, stencil, Bh, Qh, dBh;   // dBh: [2][K*Np] bed gradient; Qh: [3][K*Np] (eta hi, hu, hv); Bh, eta relative to the datum
     std::vector<int16_t> Ql;                         // [K*Np] eta lo, 16-bit (see lo_encode)
+    std::vector<int16_t> Bl;                         // [K*Np] bed (relative to the datum) lo, 16-bit
     std::vector<double> B64;                   // bed elevation, FP64, sorted order
     std::vector<int> conn;
     // time stepping state
@@ -84,8 +89,8 @@ struct dg_solver {
     int graph_key[3 * kMaxLevels] = {0};
     bool have_graph = false;
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
-    size_t prof_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events, prof_tvb_events;
+    size_t prof_used = 0, prof_tvb_used = 0;
     double prof_avg_us = 0.0;
     long long prof_launches = 0, prof_elems = 0;
 };
@@ -125,6 +130,21 @@ static float lo_decode(float hi, int16_t s) {
     return std::ldexp(float(s), e - 39);
 }
 
+// The instance's bed relative to a datum as an FP32 pair hi + lo (lo in the
+// 16-bit encoding), so that depths keep the caller's FP64 bed to 2^-16 ulp.
+static void shift_bed(dg_solver* h, const Inst& I, double datum) {
+    const int Np = h->Np;
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const size_t s0 = size_t(h->inv[I.offset + k]) * Np;
+        for (int j = 0; j < Np; ++j) {
+            const double b = h->B64[s0 + j] - datum;
+            const float bh = float(b);
+            h->Bh[s0 + j] = bh;
+            h->Bl[s0 + j] = lo_encode(bh, float(b - double(bh)));
+        }
+    }
+}
+
 static int engine_of(int precision) {
     switch (precision) {
         case DG_FUSED_MFMA32: return ENGINE_MFMA_F32;
@@ -155,6 +175,7 @@ static void compute_layout(dg_solver* h) {
     l.counters = take(64);
     l.dyn_end = o;
     l.B = take(KNp * 4);
+    l.Blo = take(KNp * 2);
     l.dB = take(2 * KNp * 4);
     l.geo = take(size_t(h->K) * 64);
     l.conn = take(size_t(h->K) * 16);
@@ -344,10 +365,11 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
 void dg_destroy(dg_solver* h) {
     if (!h) return;
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
-    for (auto& ev : h->prof_events) {
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
-    }
+    for (auto* v : {&h->prof_events, &h->prof_tvb_events})
+        for (auto& ev : *v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     if (h->exec) (void)hipStreamDestroy(h->exec);
     delete h;
 }
@@ -584,6 +606,7 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
     const size_t KNp = size_t(h->K) * Np;
     if (h->Qh.empty()) h->Qh.assign(3 * KNp, 0.f);
     if (h->Ql.empty()) h->Ql.assign(KNp, 0);
+    if (h->Bl.empty()) h->Bl.assign(KNp, 0);
     double amax = 0.0, eta_sum = 0.0;
     long long n_wet = 0;
     for (int k = 0; k < I.mesh.K; ++k) {
@@ -603,10 +626,11 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
             amax = std::fmax(amax, std::sqrt(u * u + v * v) + std::sqrt(h->p.g * d));
         }
     }
-    // datum: mean wet surface level on the 2^-22 grid, so that a bed given on
-    // that grid within distance 4 of the datum is exact in FP32 after the shift
+    // datum: mean wet surface level, rounded to the 2^-22 grid (any value
+    // serves: the bed and the level are both stored relative to it)
     I.datum = n_wet ? float(std::ldexp(std::nearbyint(std::ldexp(eta_sum / double(n_wet), 22)), -22)) : 0.f;
     const double datum = double(I.datum);
+    shift_bed(h, I, datum);
     for (int k = 0; k < I.mesh.K; ++k) {
         const int s = h->inv[I.offset + k];
         for (int j = 0; j < Np; ++j) {
@@ -614,31 +638,33 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
             const double b = h->B64[dst];
             // eta = h + B is snapped to a 2^-40 grid so that FP64 noise of the
             // caller's data (still water given as h = eta0 - B) does not reach
-            // the finely rounded eta - datum; a dry node stores its bed value
+            // the finely rounded eta - datum; the level is stored as an FP32
+            // pair hi + lo (compensated sum).  A dry node stores its bed pair,
             // and no node stores a surface below its bed
-            // the level is stored as an FP32 pair hi + lo (compensated sum)
-            const float bs = float(b - datum);
-            float es = bs, el = 0.f;
+            float es = h->Bh[dst];
+            int16_t el16 = h->Bl[dst];
             if (hh[src] > 0.0) {
                 const double eta = hh[src] + b;
                 const double snapped = std::fabs(eta) < 4096.0 ? std::nearbyint(eta * 0x1p40) * 0x1p-40 : eta;
                 const double v = snapped - datum;
-                if (v > double(bs)) {
+                if (v > b - datum) {
                     es = float(v);
-                    el = float(v - double(es));
+                    el16 = lo_encode(es, float(v - double(es)));
                 }
             }
-            h->Bh[dst] = bs;
             h->Qh[dst] = es;
             h->Qh[KNp + dst] = float(hu[src]);
             h->Qh[2 * KNp + dst] = float(hv[src]);
-            h->Ql[dst] = lo_encode(es, el);
+            h->Ql[dst] = el16;
         }
     }
     double rmin = I.mesh.inradius[0];
     for (double r : I.mesh.inradius) rmin = std::fmin(rmin, r);
     I.a_max = amax;
     I.dt_min = h->p.cfl * rmin / (double((h->p.N + 1) * (h->p.N + 1)) * std::fmax(amax, 1e-12));
+    I.staged_datum = I.datum;
+    I.staged_dt_min = I.dt_min;
+    I.staged_a_max = I.a_max;
     I.has_state = true;
     h->prepared = false;
     return DG_OK;
@@ -660,6 +686,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.nlev = h->L;
     for (int q = 0; q < 2; ++q) a.Q[q] = reinterpret_cast<float*>(h->ws + l.Q[q]);
     a.B = reinterpret_cast<const float*>(h->ws + l.B);
+    a.Blo = reinterpret_cast<const short*>(h->ws + l.Blo);
     a.dB = reinterpret_cast<const float*>(h->ws + l.dB);
     for (int s = 0; s < 3; ++s) a.R[s] = reinterpret_cast<float*>(h->ws + l.R[s]);
     a.half = h->L > 1 ? reinterpret_cast<float*>(h->ws + l.half) : nullptr;
@@ -721,6 +748,7 @@ static TvbArgs tvb_args(dg_solver* h, const StepArgs& sa) {
     t.Q[0] = sa.Q[0];
     t.Q[1] = sa.Q[1];
     t.B = sa.B;
+    t.Blo = sa.Blo;
     t.geo = sa.geo;
     t.conn = sa.conn;
     t.stencil = reinterpret_cast<const float*>(h->ws + h->lay.stencil);
@@ -787,7 +815,18 @@ static int enqueue_tick(dg_solver* h, int tick, hipStream_t s, bool limit_only) 
         TvbArgs t = tvb_args(h, a);
         t.k_begin = 0;
         t.k_end = a.k_end;
-        if (launch_tvb(t, s)) return fail(DG_EDEVICE, device_error_string());
+        std::pair<hipEvent_t, hipEvent_t>* tev = nullptr;
+        if (prof) {
+            if (h->prof_tvb_used == h->prof_tvb_events.size()) {
+                hipEvent_t e0, e1;
+                HIPCHECK(hipEventCreate(&e0));
+                HIPCHECK(hipEventCreate(&e1));
+                h->prof_tvb_events.push_back({e0, e1});
+            }
+            tev = &h->prof_tvb_events[h->prof_tvb_used++];
+        }
+        if (launch_tvb(t, s, tev ? tev->first : nullptr, tev ? tev->second : nullptr))
+            return fail(DG_EDEVICE, device_error_string());
     }
     for (int l = 0; l < m; ++l) {
         h->parity[l] ^= 1;
@@ -824,6 +863,89 @@ static bool all_started(const dg_solver* h) {
     return true;
 }
 
+// reduction arguments of instance `inst` over the current state buffers
+static DiagArgs diag_args(dg_solver* h, int inst) {
+    DiagArgs a{};
+    const Layout& l = h->lay;
+    a.K = h->K;
+    a.Np = h->Np;
+    a.k_begin = 0;
+    a.k_end = h->K;
+    a.inst = inst;
+    a.KNp = (long long)h->K * h->Np;
+    a.Q = reinterpret_cast<const float*>(h->ws + l.Q[0]);
+    a.Q2 = reinterpret_cast<const float*>(h->ws + l.Q[1]);
+    a.nlev = h->L;
+    fill_levels(h, a.lev, h->L, true);
+    a.B = reinterpret_cast<const float*>(h->ws + l.B);
+    a.Blo = reinterpret_cast<const short*>(h->ws + l.Blo);
+    a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
+    a.wfull = reinterpret_cast<const double*>(h->ws + l.wfull);
+    a.flags = reinterpret_cast<const uint8_t*>(h->ws + l.flags);
+    return a;
+}
+
+// Capture the next `period` coarse steps (the ring x ping-pong period) from
+// the current schedule state into h->graph without running them.
+static int capture_graph(dg_solver* h) {
+    constexpr int period = 6;
+    int key[3 * kMaxLevels];
+    state_key(h, key);
+    std::memcpy(h->graph_key, key, sizeof(key));
+    const long long steps0 = h->steps;
+    const int64_t ticks0 = h->ticks;
+    int saved[3][kMaxLevels];
+    for (int l = 0; l < kMaxLevels; ++l) {
+        saved[0][l] = h->parity[l];
+        saved[1][l] = h->head[l];
+        saved[2][l] = h->nhist[l];
+    }
+    HIPCHECK(hipStreamBeginCapture(h->exec, hipStreamCaptureModeThreadLocal));
+    int rc = DG_OK;
+    for (int q = 0; q < period && rc == DG_OK; ++q) rc = enqueue_coarse_step(h, h->exec);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(h->exec, &g);
+    // capture advanced the host-side schedule; the replays advance it
+    for (int l = 0; l < kMaxLevels; ++l) {
+        h->parity[l] = saved[0][l];
+        h->head[l] = saved[1][l];
+        h->nhist[l] = saved[2][l];
+    }
+    h->steps = steps0;
+    h->ticks = ticks0;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ce != hipSuccess) return fail(DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    const hipError_t ie = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(DG_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    h->have_graph = true;
+    return DG_OK;
+}
+
+extern "C" {
+
+int32_t dg_capture_graph(dg_solver* h, void* stream) {
+    if (!h) return fail(DG_EINVAL, "null handle");
+    if (!h->prepared) {
+        const int rc = dg_prepare(h, stream);
+        if (rc) return rc;
+    }
+    if (!h->p.use_graph) return fail(DG_ESTATE, "graphs are off (use_graph = 0)");
+    if (!all_started(h)) return fail(DG_ESTATE, "the Adams-Bashforth start-up (two steps) is not over");
+    HIPCHECK(hipSetDevice(h->device));
+    HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return capture_graph(h);
+}
+
+}  // extern "C"
+
 extern "C" {
 
 int32_t dg_prepare(dg_solver* h, void* stream) {
@@ -835,9 +957,18 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout& l = h->lay;
+    // back to the staged state's datum and time step (a restored checkpoint
+    // may have replaced them)
+    for (Inst& I : h->inst) {
+        if (I.datum != I.staged_datum) shift_bed(h, I, double(I.staged_datum));
+        I.datum = I.staged_datum;
+        I.dt_min = I.staged_dt_min;
+        I.a_max = I.staged_a_max;
+    }
     for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
     HIPCHECK(hipMemcpyAsync(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->ws + l.Blo, h->Bl.data(), h->Bl.size() * 2, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(h->ws + l.dB, h->dBh.data(), h->dBh.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemsetAsync(h->ws + l.dyn_begin, 0, l.dyn_end - l.dyn_begin, s));
     for (int q = 0; q < kMaxLevels; ++q) {
@@ -885,22 +1016,8 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
                 continue;
             }
             if (!h->have_graph) {
-                std::memcpy(h->graph_key, key, sizeof(key));
-                hipGraph_t g;
-                HIPCHECK(hipStreamBeginCapture(h->exec, hipStreamCaptureModeThreadLocal));
-                int rc = DG_OK;
-                for (int q = 0; q < period && rc == DG_OK; ++q) rc = enqueue_coarse_step(h, h->exec);
-                hipGraph_t gout;
-                const hipError_t ce = hipStreamEndCapture(h->exec, &gout);
+                const int rc = capture_graph(h);
                 if (rc) return rc;
-                if (ce != hipSuccess) return fail(DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-                g = gout;
-                HIPCHECK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
-                (void)hipGraphDestroy(g);
-                h->have_graph = true;
-                // capture advanced the host-side counters; undo them, the launch below replays
-                h->steps -= period;
-                h->ticks -= int64_t(period) << (h->L - 1);
             }
             hipEvent_t e0, e1;
             HIPCHECK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
@@ -1017,7 +1134,7 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
     const size_t KNp = size_t(h->K) * Np;
     const Inst& I = h->inst[inst];
     std::vector<float> q(3 * KNp), b(KNp);
-    std::vector<int16_t> ql(KNp);
+    std::vector<int16_t> ql(KNp), bl(KNp);
     for (int l = 0; l < h->L; ++l) {
         const size_t b0 = size_t(h->lev_begin[l]) * Np, n = size_t(h->lev_end[l] - h->lev_begin[l]) * Np;
         if (!n) continue;
@@ -1027,11 +1144,13 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
         HIPCHECK(hipMemcpy(ql.data() + b0, Q + 12 * KNp + b0 * 2, n * 2, hipMemcpyDeviceToHost));
     }
     HIPCHECK(hipMemcpy(b.data(), h->ws + h->lay.B, KNp * 4, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(bl.data(), h->ws + h->lay.Blo, KNp * 2, hipMemcpyDeviceToHost));
     for (int k = 0; k < I.mesh.K; ++k) {
         const size_t sidx = size_t(h->inv[I.offset + k]);
         for (int j = 0; j < Np; ++j) {
             const size_t src = sidx * Np + j, dst = size_t(k) * Np + j;
-            hh[dst] = double(q[src]) - double(b[src]) + double(lo_decode(q[src], ql[src]));
+            hh[dst] = (double(q[src]) - double(b[src])) +
+                      (double(lo_decode(q[src], ql[src])) - double(lo_decode(b[src], bl[src])));
             hu[dst] = double(q[KNp + src]);
             hv[dst] = double(q[2 * KNp + src]);
         }
@@ -1054,22 +1173,8 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
     if (!h || !d || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
     if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    DiagArgs a{};
     const Layout& l = h->lay;
-    a.K = h->K;
-    a.Np = h->Np;
-    a.k_begin = 0;
-    a.k_end = h->K;
-    a.inst = inst;
-    a.KNp = (long long)h->K * h->Np;
-    a.Q = reinterpret_cast<const float*>(h->ws + l.Q[0]);
-    a.Q2 = reinterpret_cast<const float*>(h->ws + l.Q[1]);
-    a.nlev = h->L;
-    fill_levels(h, a.lev, h->L, true);
-    a.B = reinterpret_cast<const float*>(h->ws + l.B);
-    a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
-    a.wfull = reinterpret_cast<const double*>(h->ws + l.wfull);
-    a.flags = reinterpret_cast<const uint8_t*>(h->ws + l.flags);
+    DiagArgs a = diag_args(h, inst);
     a.partial = reinterpret_cast<double*>(h->ws + l.diag_partial);
     a.out = reinterpret_cast<double*>(h->ws + l.diag_out);
     if (launch_diag(a, s)) return fail(DG_EDEVICE, device_error_string());
@@ -1091,21 +1196,39 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
 }
 
 // checkpoint blob: a 256-byte header (solver shape, per-level schedule
-// state, step and tick counts), then the device state
-static size_t ckpt_header_bytes(const dg_solver*) { return 256; }
-
-int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes) {
-    if (!h || !bytes) return fail(DG_EINVAL, "bad argument");
-    *bytes = int64_t(ckpt_header_bytes(h) + (h->lay.dyn_end - h->lay.dyn_begin));
-    return DG_OK;
-}
-
+// state, step and tick counts), one 32-byte record per instance (datum of the
+// stored levels, time step, initial wave speed, hash of the FP64 bed), then
+// the device state
 struct CkptHeader {
     uint64_t magic, K, Np, L, n_inst;
     int32_t parity[kMaxLevels], head[kMaxLevels], nhist[kMaxLevels];
     int64_t steps, ticks;
 };
 static_assert(sizeof(CkptHeader) <= 256, "checkpoint header exceeds its slot");
+struct CkptInst {
+    double datum, dt_min, a_max;
+    uint64_t bed_hash;
+};
+static constexpr uint64_t kCkptMagic = 0x4447535702ull;
+
+static size_t ckpt_prefix_bytes(const dg_solver* h) { return 256 + align256(h->inst.size() * sizeof(CkptInst)); }
+
+// FNV-1a over the instance's FP64 bed values in the caller's element order
+static uint64_t bed_hash(const dg_solver* h, int inst) {
+    const Inst& I = h->inst[inst];
+    uint64_t x = 1469598103934665603ull;
+    for (int k = 0; k < I.mesh.K; ++k) {
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(&h->B64[size_t(h->inv[I.offset + k]) * h->Np]);
+        for (size_t t = 0; t < size_t(h->Np) * 8; ++t) x = (x ^ p[t]) * 1099511628211ull;
+    }
+    return x;
+}
+
+int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes) {
+    if (!h || !bytes) return fail(DG_EINVAL, "bad argument");
+    *bytes = int64_t(ckpt_prefix_bytes(h) + (h->lay.dyn_end - h->lay.dyn_begin));
+    return DG_OK;
+}
 
 int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream) {
     int64_t need = 0;
@@ -1114,10 +1237,10 @@ int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream)
     if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
     HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     char* b = static_cast<char*>(blob);
-    const size_t hb = ckpt_header_bytes(h);
-    std::memset(b, 0, hb);
+    const size_t pb = ckpt_prefix_bytes(h);
+    std::memset(b, 0, pb);
     CkptHeader* hd = reinterpret_cast<CkptHeader*>(b);
-    hd->magic = 0x44475357u;
+    hd->magic = kCkptMagic;
     hd->K = h->K;
     hd->Np = h->Np;
     hd->L = h->L;
@@ -1129,7 +1252,14 @@ int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream)
     }
     hd->steps = h->steps;
     hd->ticks = h->ticks;
-    HIPCHECK(hipMemcpy(b + hb, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
+    CkptInst* ci = reinterpret_cast<CkptInst*>(b + 256);
+    for (size_t i = 0; i < h->inst.size(); ++i) {
+        ci[i].datum = double(h->inst[i].datum);
+        ci[i].dt_min = h->inst[i].dt_min;
+        ci[i].a_max = h->inst[i].a_max;
+        ci[i].bed_hash = bed_hash(h, int(i));
+    }
+    HIPCHECK(hipMemcpy(b + pb, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
                        hipMemcpyDeviceToHost));
     return DG_OK;
 }
@@ -1140,20 +1270,52 @@ int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* s
     if (!blob || bytes < need) return fail(DG_EINVAL, "checkpoint buffer too small");
     if (!h->prepared) return fail(DG_ESTATE, "call dg_prepare (or advance) before restoring");
     const char* b = static_cast<const char*>(blob);
-    const CkptHeader* hd = reinterpret_cast<const CkptHeader*>(b);
-    if (hd->magic != 0x44475357u || hd->K != uint64_t(h->K) || hd->Np != uint64_t(h->Np) ||
-        hd->L != uint64_t(h->L) || hd->n_inst != uint64_t(h->inst.size()))
+    CkptHeader hd;
+    std::memcpy(&hd, b, sizeof(hd));
+    if (hd.magic != kCkptMagic || hd.K != uint64_t(h->K) || hd.Np != uint64_t(h->Np) ||
+        hd.L != uint64_t(h->L) || hd.n_inst != uint64_t(h->inst.size()))
         return fail(DG_EINVAL, "checkpoint does not match this solver");
-    HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-    HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + ckpt_header_bytes(h), h->lay.dyn_end - h->lay.dyn_begin,
+    // the schedule state indexes the state ping-pong and the RHS ring
+    for (int l = 0; l < kMaxLevels; ++l)
+        if (hd.parity[l] < 0 || hd.parity[l] > 1 || hd.head[l] < 0 || hd.head[l] > 2 || hd.nhist[l] < 0 ||
+            hd.nhist[l] > 2)
+            return fail(DG_EINVAL, "corrupt checkpoint: schedule state out of range");
+    if (hd.steps < 0 || hd.ticks < 0) return fail(DG_EINVAL, "corrupt checkpoint: negative step or tick count");
+    std::vector<CkptInst> ci(h->inst.size());
+    std::memcpy(ci.data(), b + 256, ci.size() * sizeof(CkptInst));
+    for (size_t i = 0; i < ci.size(); ++i) {
+        if (!std::isfinite(ci[i].datum) || !(ci[i].dt_min > 0.0) || !std::isfinite(ci[i].dt_min) ||
+            !std::isfinite(ci[i].a_max))
+            return fail(DG_EINVAL, "corrupt checkpoint: instance " + std::to_string(i) + " record");
+        if (ci[i].bed_hash != bed_hash(h, int(i)))
+            return fail(DG_EINVAL, "checkpoint was taken over another bathymetry (instance " + std::to_string(i) + ")");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHECK(hipStreamSynchronize(s));
+    // the stored levels are relative to the checkpoint's datum and advance
+    // with its time step: rebuild the shifted bed and the time-step slot of
+    // the geometry records from them
+    const int Np = h->Np;
+    for (size_t i = 0; i < ci.size(); ++i) {
+        Inst& I = h->inst[i];
+        I.datum = float(ci[i].datum);
+        I.dt_min = ci[i].dt_min;
+        I.a_max = ci[i].a_max;
+        shift_bed(h, I, double(I.datum));
+    }
+    for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
+    HIPCHECK(hipMemcpy(h->ws + h->lay.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + h->lay.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + h->lay.Blo, h->Bl.data(), h->Bl.size() * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + ckpt_prefix_bytes(h), h->lay.dyn_end - h->lay.dyn_begin,
                        hipMemcpyHostToDevice));
     for (int l = 0; l < kMaxLevels; ++l) {
-        h->parity[l] = hd->parity[l];
-        h->head[l] = hd->head[l];
-        h->nhist[l] = hd->nhist[l];
+        h->parity[l] = hd.parity[l];
+        h->head[l] = hd.head[l];
+        h->nhist[l] = hd.nhist[l];
     }
-    h->steps = hd->steps;
-    h->ticks = hd->ticks;
+    h->steps = hd.steps;
+    h->ticks = hd.ticks;
     return DG_OK;
 }
 
@@ -1161,22 +1323,27 @@ int32_t dg_set_profiling(dg_solver* h, int32_t on) {
     if (!h) return fail(DG_EINVAL, "null handle");
     h->profiling = on != 0;
     h->prof_used = 0;
+    h->prof_tvb_used = 0;
     h->prof_elems = 0;
     return DG_OK;
 }
 
-int32_t dg_kernel_timing(const dg_solver* hc, double* avg_us, int64_t* launches, int64_t* elems) {
-    if (!hc) return fail(DG_EINVAL, "null handle");
+int32_t dg_kernel_timing(const dg_solver* hc, int32_t which, double* avg_us, int64_t* launches,
+                         int64_t* elems) {
+    if (!hc || (which != 0 && which != 1)) return fail(DG_EINVAL, "null handle or unknown kernel id");
     dg_solver* h = const_cast<dg_solver*>(hc);
+    const auto& evs = which == 0 ? h->prof_events : h->prof_tvb_events;
+    const size_t used = which == 0 ? h->prof_used : h->prof_tvb_used;
     double tot = 0.0;
-    for (size_t i = 0; i < h->prof_used; ++i) {
-        HIPCHECK(hipEventSynchronize(h->prof_events[i].second));
+    for (size_t i = 0; i < used; ++i) {
+        HIPCHECK(hipEventSynchronize(evs[i].second));
         float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, h->prof_events[i].first, h->prof_events[i].second));
+        HIPCHECK(hipEventElapsedTime(&ms, evs[i].first, evs[i].second));
         tot += ms;
     }
-    if (avg_us) *avg_us = h->prof_used ? tot * 1000.0 / h->prof_used : 0.0;
-    if (launches) *launches = (int64_t)h->prof_used;
+    if (avg_us) *avg_us = used ? tot * 1000.0 / used : 0.0;
+    if (launches) *launches = (int64_t)used;
+    // the TVB kernel of a tick covers the same element range as its step kernel
     if (elems) *elems = h->prof_used ? (h->prof_elems + (long long)h->prof_used / 2) / (long long)h->prof_used : 0;
     return DG_OK;
 }

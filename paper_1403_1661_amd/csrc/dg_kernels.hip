@@ -1,8 +1,8 @@
 // HIP kernels (gfx950) of the nodal DG shallow-water step.
 //
 // Step kernel (one workgroup = E consecutive elements, one lane per node):
-//   1. stage eta (an FP32 hi + lo pair), hu, hv, B of the block's elements
-//      in LDS (coalesced element-major loads);
+//   1. stage eta and B (each an FP32 hi + lo pair), hu, hv of the block's
+//      elements in LDS (coalesced element-major loads);
 //   2. volume fluxes at the nodes in contravariant form X_r = rx F + ry G,
 //      velocities 2 h m / (h^2 + max(h^2, hvel^2)) (m/h for h >= hvel),
 //      X_s = sx F + sy G (Section 2, Eq. 2.3), with the momentum pressure and
@@ -103,6 +103,14 @@ __device__ __forceinline__ float depth_jump(float etaM, float loM, float etaP, f
     return (hsM > 0.f && hsP > 0.f) ? (etaM - etaP) + (loM - loP) : hsM - hsP;
 }
 
+// Higher of two compensated bed values (hi + lo), for h* = eta - max(B-, B+)
+// of Eq. 5.1: equal high words compare by the low words.
+__device__ __forceinline__ void bed_max(float bM, float lM, float bP, float lP, float& b, float& l) {
+    const bool m = bM > bP || (bM == bP && lM >= lP);
+    b = m ? bM : bP;
+    l = m ? lM : lP;
+}
+
 template <typename A>
 __device__ __forceinline__ int level_of(const A& a, int k) {
     int l = 0;
@@ -129,9 +137,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, E = S::E;
     __shared__ float sDr[Np * Np], sDs[Np * Np], sL[Np * nF];
     __shared__ int sFm[nF];
-    __shared__ float sQ[5][E * Np];       // eta (hi), hu, hv, B, eta (lo)
+    __shared__ float sQ[6][E * Np];       // eta (hi), hu, hv, B (hi), eta (lo), B (lo)
     __shared__ float sX[6][E * Np];       // X_r (3 fields), X_s (3 fields)
-    __shared__ float sT[5][E * nF];       // exterior eta (hi), hu, hv, B, eta (lo)
+    __shared__ float sT[6][E * nF];       // exterior eta (hi), hu, hv, B (hi), eta (lo), B (lo)
     __shared__ float sLam[E * nF];
     __shared__ float sF[3][E * nF];
     __shared__ double sRed[E][16];
@@ -159,7 +167,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     const float g = a.g, hvel = a.hvel;
 
     LevelArgs L = a.lev[0];
-    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f, lo = 0.f;
+    float eta = 0.f, hu = 0.f, hv = 0.f, Bn = 0.f, lo = 0.f, bl = 0.f;
     float4 g0 = make_float4(0, 0, 0, 0), g3 = make_float4(0, 0, 0, 0);
     const long long idx = (long long)k * Np + i;
     if (live) {
@@ -170,11 +178,13 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         hv = Q[2 * KNp + idx];
         lo = lo_decode(eta, reinterpret_cast<const short*>(Q + 3 * KNp)[idx]);
         Bn = a.B[idx];
+        bl = lo_decode(Bn, a.Blo[idx]);
         sQ[0][tid] = eta;
         sQ[1][tid] = hu;
         sQ[2][tid] = hv;
         sQ[3][tid] = Bn;
         sQ[4][tid] = lo;
+        sQ[5][tid] = bl;
         const float4* gp = reinterpret_cast<const float4*>(a.geo) + 4LL * k;
         g0 = gp[0];   // rx, ry, sx, sy
         g3 = gp[3];   // fs2, J, dt_min of the instance, instance id
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     if (rhs) {
         // ---- volume fluxes at the nodes
         if (live) {
-            const float h = (eta - Bn) + lo;
+            const float h = (eta - Bn) + (lo - bl);
             dlt = (eta - sQ[0][e * Np]) + (lo - sQ[4][e * Np]);
             const float fv = vel_factor(h, hvel);
             const float u = hu * fv;
@@ -216,8 +226,8 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             const int n = sFm[fn];
             const float etaM = sQ[0][fe * Np + n], huM = sQ[1][fe * Np + n];
             const float hvM = sQ[2][fe * Np + n], BM = sQ[3][fe * Np + n];
-            const float loM = sQ[4][fe * Np + n];
-            float etaP, huP, hvP, BP, loP = 0.f;
+            const float loM = sQ[4][fe * Np + n], blM = sQ[5][fe * Np + n];
+            float etaP, huP, hvP, BP, loP = 0.f, blP;
             if (nb < 0) {
                 const float* gk = a.geo + 16LL * kk;
                 const float nx = gk[4 + f], ny = gk[7 + f];
@@ -225,6 +235,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 etaP = etaM;
                 loP = loM;
                 BP = BM;
+                blP = blM;
                 huP = huM - 2.f * mn * nx;
                 hvP = hvM - 2.f * mn * ny;
             } else {
@@ -234,6 +245,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 const int n2 = sFm[f2 * Nfp + (Nfp - 1 - j)];
                 const long long id2 = (long long)nb * Np + n2;
                 BP = a.B[id2];
+                blP = lo_decode(BP, a.Blo[id2]);
                 if (L2.active || a.half == nullptr) {
                     const float* Q2 = a.Q[L2.parity];
                     etaP = Q2[id2];
@@ -252,15 +264,18 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             sT[2][t] = hvP;
             sT[3][t] = BP;
             sT[4][t] = loP;
+            sT[5][t] = blP;
             // nodal wave speed of the reconstructed states
             const float* gk = a.geo + 16LL * kk;
             const float nx = gk[4 + f], ny = gk[7 + f];
-            const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
+            const float hM = (etaM - BM) + (loM - blM), hP = (etaP - BP) + (loP - blP);
             const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
             const float uM = huM * fM, vM = hvM * fM;
             const float uP = huP * fP, vP = hvP * fP;
-            const float Bmax = fmaxf(BM, BP);
-            const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
+            float Bmax, bmlo;
+            bed_max(BM, blM, BP, blP, Bmax, bmlo);
+            const float hsM = fmaxf(0.f, (etaM - Bmax) + (loM - bmlo));
+            const float hsP = fmaxf(0.f, (etaP - Bmax) + (loP - bmlo));
             const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
             sLam[t] = fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP));
         }
@@ -280,14 +295,17 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             const float hvM = sQ[2][fe * Np + n], BM = sQ[3][fe * Np + n];
             const float etaP = sT[0][t], huP = sT[1][t], hvP = sT[2][t], BP = sT[3][t];
             const float loM = sQ[4][fe * Np + n], loP = sT[4][t];
+            const float blM = sQ[5][fe * Np + n], blP = sT[5][t];
             const float* gk = a.geo + 16LL * kk;
             const float nx = gk[4 + f], ny = gk[7 + f], fs = gk[10 + f];
-            const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
+            const float hM = (etaM - BM) + (loM - blM), hP = (etaP - BP) + (loP - blP);
             const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
             const float uM = huM * fM, vM = hvM * fM;
             const float uP = huP * fP, vP = hvP * fP;
-            const float Bmax = fmaxf(BM, BP);
-            const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
+            float Bmax, bmlo;
+            bed_max(BM, blM, BP, blP, Bmax, bmlo);
+            const float hsM = fmaxf(0.f, (etaM - Bmax) + (loM - bmlo));
+            const float hsP = fmaxf(0.f, (etaP - Bmax) + (loP - bmlo));
             const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
             // F(Q-).n - F*.n.  The (g/2)(h-)^2 of F(Q-).n cancels the one in the
             // pressure correction of Eq. 5.2, and the remaining (g/2) h*^2 terms
@@ -396,12 +414,12 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
             if (q == 0) {
                 acc = 1e300;
                 for (int j = 0; j < Np; ++j)
-                    acc = fmin(acc, (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]);
+                    acc = fmin(acc, ((double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]) + ((double)sQ[4][e * Np + j] - (double)sQ[5][e * Np + j]));
             } else if (q < 4) {
                 const int c = q - 1;
                 acc = 0.0;
                 for (int j = 0; j < Np; ++j) {
-                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]
+                    const double val = c == 0 ? ((double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]) + ((double)sQ[4][e * Np + j] - (double)sQ[5][e * Np + j])
                                               : (double)sQ[c][e * Np + j];
                     acc += a.ops.wh[j] * val;
                 }
@@ -409,7 +427,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                 const int c = (q - 4) / 3, ed = (q - 4) % 3;
                 acc = 0.0;
                 for (int j = 0; j < Np; ++j) {
-                    const double val = c == 0 ? (double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j] + (double)sQ[4][e * Np + j]
+                    const double val = c == 0 ? ((double)sQ[0][e * Np + j] - (double)sQ[3][e * Np + j]) + ((double)sQ[4][e * Np + j] - (double)sQ[5][e * Np + j])
                                               : (double)sQ[c][e * Np + j];
                     acc += a.ops.pmid[ed * Np + j] * val;
                 }
@@ -463,7 +481,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     float out[3] = {qn[0], qn[1], qn[2]};
     float olo = qlo;
     if (code == 2) {
-        eta_split(sRed[e][15] + (double)Bn, out[0], olo);
+        eta_split(sRed[e][15] + ((double)Bn + (double)bl), out[0], olo);
         out[1] = 0.f;
         out[2] = 0.f;
     } else if (code == 1) {
@@ -474,12 +492,12 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 #pragma unroll
             for (int ed = 0; ed < 3; ++ed) val += th * sRed[e][4 + 3 * c + ed] * a.ops.phi[ed * Np + i];
             if (c == 0)
-                eta_split(val + (double)Bn, out[0], olo);
+                eta_split(val + ((double)Bn + (double)bl), out[0], olo);
             else
                 out[c] = (float)val;
         }
     }
-    if (a.thin_cut > 0.f && (out[0] - Bn) + olo < a.thin_cut) {   // thin film: no momentum
+    if (a.thin_cut > 0.f && (out[0] - Bn) + (olo - bl) < a.thin_cut) {   // thin film: no momentum
         out[1] = 0.f;
         out[2] = 0.f;
     }
@@ -772,6 +790,7 @@ step_mfma_kernel(StepArgs a) {
     const float* r_prev2 = MULTI ? a.R[L.slot[2]] : a.r_prev2;
     const unsigned QB = 3u * FB + 2u * KNp;   // state buffer: hi, hu, hv (FP32), lo (16-bit)
     const BufF32 bQi(q_in, QB), bQo(q_out, QB), bB(a.B, FB), bdB(a.dB, 2u * FB);
+    const BufF32 bBl(reinterpret_cast<const float*>(a.Blo), 2u * KNp);
     const BufF32 bR0(r_now, 3u * FB), bR1(r_prev1, 3u * FB), bR2(r_prev2, 3u * FB);
     float r1[3], r2[3];
     const float eta = bQi.ld(idx, 0);
@@ -779,6 +798,7 @@ step_mfma_kernel(StepArgs a) {
     const float hv = bQi.ld(idx, 2u * FB);
     const float lo = lo_decode(eta, bQi.ld16(idx, 3u * FB));
     const float Bn = bB.ld(idx, 0);
+    const float bl = lo_decode(Bn, bBl.ld16(idx, 0));
     const float dBx = bdB.ld(idx, 0);   // static bed gradient
     const float dBy = bdB.ld(idx, FB);
     // the RHS history is read unconditionally (slots hold zeros or finite RHS
@@ -802,6 +822,7 @@ step_mfma_kernel(StepArgs a) {
     const int nbc = nb >= 0 ? nb : kc;
     const unsigned id2 = (unsigned)nbc * Np + face_node<N>(f2 * Nfp + (Nfp - 1 - jj));
     float BP = bB.ld(id2, 0);
+    float blP = lo_decode(BP, bBl.ld16(id2, 0));
     float etaP, huP, hvP, loP = 0.f;
     const unsigned HB = 4u * (unsigned)a.KnF;   // bytes of one half-trace field
     const BufF32 bH(a.half, 3u * HB);
@@ -848,7 +869,7 @@ step_mfma_kernel(StepArgs a) {
     // computes (lanes that are not nodes hold a clamped node's finite data)
     // and lanes that are not nodes store into the unread padding of the row.
     {
-        const float h = (eta - Bn) + lo;
+        const float h = (eta - Bn) + (lo - bl);
         const float fv = 2.f * h * __builtin_amdgcn_rcpf(h * h + fmaxf(h * h, hvel * hvel));
         const float u = hu * fv, v = hv * fv;
         const float p = 0.5f * g * (dlt * (2.f * h - dlt));
@@ -944,20 +965,24 @@ step_mfma_kernel(StepArgs a) {
     const float hvM = __shfl(hv, gbase + n);
     const float BM = __shfl(Bn, gbase + n);
     const float loM = __shfl(lo, gbase + n);
+    const float blM = __shfl(bl, gbase + n);
     if (nb < 0) {
         const float mn = huM * nx + hvM * ny;
         etaP = etaM;
         loP = loM;
         BP = BM;
+        blP = blM;
         huP = huM - 2.f * mn * nx;
         hvP = hvM - 2.f * mn * ny;
     }
-    const float hM = (etaM - BM) + loM, hP = (etaP - BP) + loP;
+    const float hM = (etaM - BM) + (loM - blM), hP = (etaP - BP) + (loP - blP);
     const float fM = 2.f * hM * __builtin_amdgcn_rcpf(hM * hM + fmaxf(hM * hM, hvel * hvel));
     const float fP = 2.f * hP * __builtin_amdgcn_rcpf(hP * hP + fmaxf(hP * hP, hvel * hvel));
     const float uM = huM * fM, vM = hvM * fM, uP = huP * fP, vP = hvP * fP;
-    const float Bmax = fmaxf(BM, BP);
-    const float hsM = fmaxf(0.f, (etaM - Bmax) + loM), hsP = fmaxf(0.f, (etaP - Bmax) + loP);
+    float Bmax, bmlo;
+    bed_max(BM, blM, BP, blP, Bmax, bmlo);
+    const float hsM = fmaxf(0.f, (etaM - Bmax) + (loM - bmlo));
+    const float hsP = fmaxf(0.f, (etaP - Bmax) + (loP - bmlo));
     const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
     const float lamN = fnode ? fmaxf(fabsf(unM) + __builtin_amdgcn_sqrtf(g * hsM),
                                      fabsf(unP) + __builtin_amdgcn_sqrtf(g * hsP))
@@ -1075,7 +1100,7 @@ step_mfma_kernel(StepArgs a) {
         }
     }
     // ---- FP64 element reductions on the matrix cores, min depth by shuffles
-    const double h64 = node ? (double)qn[0] - (double)Bn + (double)qlo : 0.0;
+    const double h64 = node ? ((double)qn[0] - (double)Bn) + ((double)qlo - (double)bl) : 0.0;
     wave_lds_sync();   // X^T / result reads done before the node values overwrite them
     sVd[q][0][j] = h64;
     sVd[q][1][j] = node ? (double)qn[1] : 0.0;
@@ -1152,7 +1177,7 @@ step_mfma_kernel(StepArgs a) {
     float out[3] = {qn[0], qn[1], qn[2]};
     float olo = qlo;
     if (code == 2) {
-        eta_split(hdry + (double)Bn, out[0], olo);
+        eta_split(hdry + ((double)Bn + (double)bl), out[0], olo);
         out[1] = 0.f;
         out[2] = 0.f;
     } else if (code == 1) {
@@ -1162,12 +1187,12 @@ step_mfma_kernel(StepArgs a) {
 #pragma unroll
             for (int ed = 0; ed < 3; ++ed) val += scale * sRed[q][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
             if (c == 0)
-                eta_split(val + (double)Bn, out[0], olo);
+                eta_split(val + ((double)Bn + (double)bl), out[0], olo);
             else
                 out[c] = (float)val;
         }
     }
-    if (a.thin_cut > 0.f && (out[0] - Bn) + olo < a.thin_cut) {   // thin film: no momentum
+    if (a.thin_cut > 0.f && (out[0] - Bn) + (olo - bl) < a.thin_cut) {   // thin film: no momentum
         out[1] = 0.f;
         out[2] = 0.f;
     }
@@ -1319,7 +1344,8 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         const long long id = (long long)k * Np + j;
         const double hval = qb[0] + D[0][0] * p0 + D[0][1] * p1 + D[0][2] * p2;
         float hi, lo;
-        eta_split(hval + (double)a.B[id], hi, lo);
+        const float bh = a.B[id];
+        eta_split(hval + ((double)bh + (double)lo_decode(bh, a.Blo[id])), hi, lo);
         Qo[id] = hi;
         reinterpret_cast<short*>(Qo + 3 * a.KNp)[id] = lo_encode(hi, lo);
         const bool thin = a.thin_cut > 0.0 && hval < a.thin_cut;   // thin film: no momentum
@@ -1349,8 +1375,9 @@ __global__ void __launch_bounds__(256) diag_partial_kernel(DiagArgs a) {
         double wh = 0.0;
         for (int j = 0; j < a.Np; ++j) {
             const long long id = (long long)k * a.Np + j;
-            const double h = (double)Q[id] - (double)a.B[id] +
-                             (double)lo_decode(Q[id], reinterpret_cast<const short*>(Q + 3 * a.KNp)[id]);
+            const double h = ((double)Q[id] - (double)a.B[id]) +
+                             ((double)lo_decode(Q[id], reinterpret_cast<const short*>(Q + 3 * a.KNp)[id]) -
+                              (double)lo_decode(a.B[id], a.Blo[id]));
             wh += a.wfull[j] * h;
             hmin = fmin(hmin, h);
         }
@@ -1503,11 +1530,15 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
     }
 }
 
-int launch_tvb(const TvbArgs& a, void* stream) {
+int launch_tvb(const TvbArgs& a, void* stream, void* ev_start, void* ev_stop) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), a);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ev_start)
+        hipExtLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0, s,
+                              static_cast<hipEvent_t>(ev_start), static_cast<hipEvent_t>(ev_stop), 0, a);
+    else
+        hipLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a);
     return check_launch("tvb kernel");
 }
 

@@ -73,7 +73,8 @@ struct StepArgs {
     LevelArgs lev[kMaxLevels];
     float* Q[2];           // ping-pong state buffers: [3][K*Np] FP32 eta (hi), hu, hv, then
                            // [K*Np] 16-bit eta (lo) at float offset 3 K*Np
-    const float* B;        // [K*Np]
+    const float* B;        // [K*Np] bed relative to the datum, FP32 high word
+    const short* Blo;      // [K*Np] its low word, 16-bit (encoding of the level's low word)
     const float* dB;       // [2][K*Np] dB/dx, dB/dy at the nodes (static, from FP64 on the host)
     float* R[3];           // ring slots [3][K*Np]
     // single rate: the level's buffers resolved on the host (state in / out,
@@ -113,6 +114,7 @@ struct TvbArgs {
     LevelArgs lev[kMaxLevels];
     float* Q[2];
     const float* B;
+    const short* Blo;
     const float* geo;
     const int* conn;
     const float* stencil;  // [K][16]
@@ -133,6 +135,7 @@ struct DiagArgs {
     int nlev;
     LevelArgs lev[kMaxLevels];
     const float* B;
+    const short* Blo;
     const float* geo;
     const double* wfull;   // Np: w
     const uint8_t* flags;
@@ -143,7 +146,7 @@ struct DiagArgs {
 // ev_start / ev_stop (hipEvent_t, optional): timestamps of the kernel itself
 int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_start = nullptr,
                 void* ev_stop = nullptr);
-int launch_tvb(const TvbArgs& a, void* stream);
+int launch_tvb(const TvbArgs& a, void* stream, void* ev_start = nullptr, void* ev_stop = nullptr);
 int launch_diag(const DiagArgs& a, void* stream);
 // elements per block: matrix-core kernel 1, 2 or 4 waves of 64 / lanes
 // elements (N = 1, 2, 4: 4, 8, 16; N = 3: 5, 10, 20; N = 5: 3, 6, 12),

@@ -32,7 +32,7 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_destroy", "dg_last_error", "dg_
            "dg_advance", "dg_get_state", "dg_get_connectivity", "dg_get_levels",
            "dg_get_tvb_stencil", "dg_get_flags", "dg_get_diagnostics", "dg_checkpoint_bytes",
            "dg_get_checkpoint", "dg_set_checkpoint", "dg_set_profiling", "dg_kernel_timing",
-           "dg_autotune"]
+           "dg_autotune", "dg_capture_graph"]
 
 
 class DGError(RuntimeError):
@@ -107,7 +107,8 @@ def load_library(path: Optional[str] = None):
         "dg_get_checkpoint": (_I32, [_P, _P, _I64, _P]),
         "dg_set_checkpoint": (_I32, [_P, _P, _I64, _P]),
         "dg_set_profiling": (_I32, [_P, _I32]),
-        "dg_kernel_timing": (_I32, [_P, _D, C.POINTER(_I64), C.POINTER(_I64)]),
+        "dg_kernel_timing": (_I32, [_P, _I32, _D, C.POINTER(_I64), C.POINTER(_I64)]),
+        "dg_capture_graph": (_I32, [_P, _P]),
         "dg_autotune": (_I32, [_P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _D, _P]),
     }
     for name, (res, args) in sig.items():
@@ -319,12 +320,17 @@ class Solver:
     def set_profiling(self, on: bool):
         _check(self.lib.dg_set_profiling(self.h, 1 if on else 0))
 
-    def kernel_timing(self):
+    def kernel_timing(self, which: int = 0):
+        """(average us, launches, elements per launch) of the step kernel
+        (which = 0) or the TVB kernel (which = 1) over the profiling region."""
         us = C.c_double()
         n = _I64()
         e = _I64()
-        _check(self.lib.dg_kernel_timing(self.h, C.byref(us), C.byref(n), C.byref(e)))
+        _check(self.lib.dg_kernel_timing(self.h, int(which), C.byref(us), C.byref(n), C.byref(e)))
         return us.value, n.value, e.value
+
+    def capture_graph(self, stream=None):
+        _check(self.lib.dg_capture_graph(self.h, C.c_void_p(self._stream(stream))))
 
     def autotune(self, reps: int = 10, stream=None):
         """Time each elements-per-block candidate of the step kernel on the

@@ -14,11 +14,18 @@ c4: the 1048576-triangle N=5 fully wet precision workload for its
 configured 300 steps (about 90 minutes on 8 cores, 11 GB); the same record
 for 1024 sampled elements.
 
-c3: the 496098-triangle graded band mesh with 4 multi-rate levels for 10
-coarse steps (80 ticks) of the full run; the same record plus the level of
-every element.
+c3: the 496098-triangle graded band mesh with 4 multi-rate levels for its
+configured 100 coarse steps (800 finest-level ticks); the same record plus
+the level of every element.
 
-    python tests/golden/make_golden.py c3 c4
+c5: the 64-instance ensemble, every instance run by its own oracle (the
+instances are independent, each with its own time step) for the configured
+200 steps; 64 elements sampled from each instance (numpy.random.default_rng
+seeded 2024 + instance number), with their final state, Jacobians, the
+instance's mass and time step and the sampled elements' final limiter codes.
+Runs the instances in a process pool (one BLAS thread each).
+
+    python tests/golden/make_golden.py c3 c4 c5
 """
 import os
 import sys
@@ -85,6 +92,46 @@ def make_sampled(name, wl, steps, n_samples=1024):
     print("wrote", out, f"{time.time() - t0:.0f}s", flush=True)
 
 
+def _c5_instance(args):
+    i, n_samples = args
+    wl = W.c5()
+    ins = wl.instances[i]
+    s = Solver(ins.vx, ins.vy, ins.etov, wl.N, Params(g=wl.g, cfl=wl.cfl))
+    x, y = s.nodes()
+    s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry))
+    m0 = s.mass()
+    t0 = time.time()
+    for _ in range(wl.steps):
+        s.step()
+    rng = np.random.default_rng(2024 + i)
+    idx = np.sort(rng.choice(s.K, size=min(n_samples, s.K), replace=False))
+    print(f"c5[{i}] K={s.K} {wl.steps} steps {time.time() - t0:.0f}s", flush=True)
+    return dict(elements=idx, h=s.q[0][idx], hu=s.q[1][idx], hv=s.q[2][idx], J=s.mesh.J[idx],
+                mass0=m0, mass=s.mass(), dt=s.dt_min, final_pp=s.flags.pp[idx],
+                final_tvb=s.flags.tvb[idx], M=s.ref.M)
+
+
+def make_c5(n_samples=64, workers=4):
+    """Every instance of the ensemble through its own oracle; the records
+    are stacked along a leading instance axis."""
+    from concurrent.futures import ProcessPoolExecutor
+    from threadpoolctl import threadpool_limits
+    n_inst = len(W.c5().instances)
+    with threadpool_limits(limits=1), ProcessPoolExecutor(max_workers=workers) as ex:
+        recs = list(ex.map(_c5_instance, [(i, n_samples) for i in range(n_inst)]))
+    out = os.path.join(HERE, "c5_oracle_samples.npz")
+    np.savez_compressed(out, elements=np.stack([r["elements"] for r in recs]),
+                        h=np.stack([r["h"] for r in recs]), hu=np.stack([r["hu"] for r in recs]),
+                        hv=np.stack([r["hv"] for r in recs]), J=np.stack([r["J"] for r in recs]),
+                        mass_matrix=recs[0]["M"], steps=W.c5().steps,
+                        mass0=np.array([r["mass0"] for r in recs]), mass=np.array([r["mass"] for r in recs]),
+                        dt=np.array([r["dt"] for r in recs]),
+                        final_pp=np.stack([r["final_pp"] for r in recs]),
+                        final_tvb=np.stack([r["final_tvb"] for r in recs]),
+                        command="python tests/golden/make_golden.py c5")
+    print("wrote", out, flush=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if not args:
@@ -93,8 +140,10 @@ if __name__ == "__main__":
         if a == "c2":
             make_c2()
         elif a == "c3":
-            make_sampled("c3", W.c3(), 10)
+            make_sampled("c3", W.c3(), 100)
         elif a == "c4":
             make_sampled("c4", W.c4(), 300)
+        elif a == "c5":
+            make_c5()
         else:
             print(__doc__)

@@ -24,7 +24,7 @@ def _require_gpu():
 
 
 def _bed(x, y):
-    return W.on_bed_grid(0.3 * np.asarray(x) + 0.1 * np.asarray(y))
+    return 0.3 * np.asarray(x) + 0.1 * np.asarray(y)
 
 
 def _tiny(n_cells_x: int, n_cells_y: int, split_one: bool = False):
@@ -289,3 +289,23 @@ def test_host_side_input_errors():
         other.restore(blob + bytes(max(0, len(other.checkpoint()) - len(blob))))
     assert e.value.code == -1
     g.restore(blob)                                    # its own blob still restores
+    # a corrupt schedule state (state parity 5 at byte 40 of the header) is
+    # rejected before anything is copied to the device
+    bad_blob = bytearray(blob)
+    bad_blob[40:44] = (5).to_bytes(4, "little", signed=True)
+    with pytest.raises(dgswe.DGError) as e:
+        g.restore(bytes(bad_blob))
+    assert e.value.code == -1
+    bad_blob = bytearray(blob)
+    bad_blob[40 + 24:40 + 28] = (3).to_bytes(4, "little", signed=True)   # ring head 3
+    with pytest.raises(dgswe.DGError) as e:
+        g.restore(bytes(bad_blob))
+    assert e.value.code == -1
+    # a blob taken over another bathymetry is rejected
+    h2 = gpu_solver(_workload([_tiny(2, 2), _tiny(3, 2)], 2))
+    h2.set_bathymetry(0, 0.01 * np.ones_like(x))
+    h2.set_state(0, h, 0 * h, 0 * h)
+    h2.prepare()
+    with pytest.raises(dgswe.DGError) as e:
+        h2.restore(blob)
+    assert e.value.code == -1

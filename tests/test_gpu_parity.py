@@ -179,6 +179,37 @@ def test_checkpoint_resume_and_determinism():
         assert np.array_equal(x, y)
 
 
+def test_checkpoint_restores_onto_solver_started_from_get_state():
+    """A restart from the state read back at the checkpoint: the new solver's
+    own dg_set_state picks another datum and time step (from the evolved
+    state), and restoring the blob replaces both, so the run continues bit
+    for bit and the reported time is the checkpoint's."""
+    _require_gpu()
+    wl = W.small_wetdry(n=10, N=3)
+    log("[checkpoint-restart]")
+    a = gpu_solver(wl)
+    a.advance(25)
+    blob = a.checkpoint()
+    snap = a.get_state(0)
+    a.advance(25)
+    ref = a.get_state(0)
+    from paper_1403_1661_amd import dgswe
+    ins = wl.instances[0]
+    b = dgswe.Solver([(ins.vx, ins.vy, ins.etov)], wl.N, g=wl.g, cfl=wl.cfl, precision="fused_fp32")
+    b.bind("cuda:0")
+    x, y = b.node_coords(0)
+    b.set_bathymetry(0, ins.bathymetry(x, y))
+    b.set_state(0, *snap)
+    b.prepare()
+    assert b.levels(0)[1] != a.levels(0)[1]
+    b.restore(blob)
+    assert b.levels(0)[1] == a.levels(0)[1]
+    b.advance(25)
+    for p_, q_ in zip(ref, b.get_state(0)):
+        assert np.array_equal(p_, q_)
+    assert b.diagnostics(0)["time"] == a.diagnostics(0)["time"]
+
+
 @pytest.mark.parametrize("case", ["multirate", "ensemble12"])
 def test_checkpoint_resume_multirate_and_ensemble(case):
     """Checkpoints of the multi-rate schedule (per-level history, parity and

@@ -48,6 +48,29 @@ def test_lake_at_rest_discontinuous_bed():
     assert np.max(np.abs(s.rhs(q, B))) < 1e-12
 
 
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_stepped_bed_workloads(N):
+    """The stepped-bed inputs of the GPU tests (a bed piece per element, a
+    jump at every face): still water is a steady state of the oracle; over the
+    ledge, whose dry elements' bed rises above the wet neighbours' surface, a
+    wave conserves mass and keeps depths non-negative, and the ledge's faces
+    are where Eq. 5.1 clips the reconstructed depth to zero."""
+    s = make(W.stepped_bed("lake", N=N))
+    assert np.max(np.abs(s.rhs(s.q, s.B))) < 1e-11
+    s = make(W.stepped_bed("ledge", N=N))
+    x, _ = s.nodes()
+    eta = s.q[0] + s.B
+    wet = s.q[0].min(axis=1) > 0.0
+    nb = s.mesh.etoe
+    above = [k for k in range(s.K) if wet[k] and any(not wet[nb[k, f]] and s.B[nb[k, f]].min() > eta[k].max()
+                                                      for f in range(3))]
+    assert len(above) >= 4
+    m0 = s.mass()
+    s.run(100)
+    assert abs(s.mass() - m0) <= 1e-13 * m0
+    assert s.q[0].min() >= 0.0
+
+
 def test_uniform_flow_interior_residual_zero():
     wl = W.lake_at_rest(n=6, N=3)
     ins = wl.instances[0]

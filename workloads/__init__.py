@@ -25,10 +25,8 @@ Workloads (all seeded with ``numpy.random.default_rng(seed)``):
           200 steps each.
 
 Bathymetry ``B`` is bed elevation; the free surface is ``eta = h + B``.
-Every bathymetry function returns values on a 2^-22 grid (about 2.4e-7 in the
-units of the problem): such a bed is represented exactly by a single FP32
-value relative to any datum on the same grid within distance 4, so the FP32
-device and the FP64 oracle see the same bed.
+Bathymetry functions return plain FP64 values (no rounding to a grid the FP32
+device could represent exactly).
 """
 from __future__ import annotations
 
@@ -39,12 +37,6 @@ from typing import Callable, List, Optional
 import numpy as np
 
 G_DEFAULT = 9.81
-BED_GRID = 2.0 ** -22
-
-
-def on_bed_grid(b):
-    """Round bed elevations to the 2^-22 grid."""
-    return np.rint(np.asarray(b, dtype=np.float64) / BED_GRID) * BED_GRID
 
 
 @dataclass
@@ -201,7 +193,7 @@ def beach_bathymetry(rng: np.random.Generator, n_bumps: int = 8, slope: float = 
         b = slope * x
         for k in range(n_bumps):
             b = b + amp * np.exp(-((x - cx[k]) ** 2 + (y - cy[k]) ** 2) / width ** 2)
-        return on_bed_grid(b)
+        return b
 
     return bath, (cx, cy)
 
@@ -231,7 +223,7 @@ def c3(n0: int = 54, seed: int = 3, n_bands: int = 4) -> Workload:
     L = float(n_bands)
 
     def bath(x, y):
-        return on_bed_grid(0.9 * (np.asarray(x, dtype=np.float64) / L) ** 2)
+        return 0.9 * (np.asarray(x, dtype=np.float64) / L) ** 2
 
     def init(x, y):
         x = np.asarray(x, dtype=np.float64)
@@ -266,7 +258,7 @@ def fourier_bathymetry(rng: np.random.Generator, n_modes: int = 16, amp: float =
     fmax = float(np.max(np.abs(f(gx, gy))))
 
     def bath(x, y):
-        return on_bed_grid(-mean_depth + amp * f(x, y) / fmax)
+        return -mean_depth + amp * f(x, y) / fmax
 
     return bath
 
@@ -299,7 +291,7 @@ def c5(n_inst: int = 64, seed: int = 5, kmin: float = 1e4, kmax: float = 2e5) ->
         cx, cy = rng.uniform(0.0, 1.0, size=2)
 
         def bath(x, y, slope=slope):
-            return on_bed_grid(slope * np.asarray(x, dtype=np.float64))
+            return slope * np.asarray(x, dtype=np.float64)
 
         def init(x, y, slope=slope, amp=amp, cx=cx, cy=cy):
             x = np.asarray(x, dtype=np.float64)
@@ -321,7 +313,7 @@ def lake_at_rest(n: int = 4, N: int = 3, jitter: float = 0.2, seed: int = 11,
     def bath(x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        return on_bed_grid(0.2 * np.sin(2.0 * np.pi * x) * np.cos(np.pi * y) + 0.1 * x * y)
+        return 0.2 * np.sin(2.0 * np.pi * x) * np.cos(np.pi * y) + 0.1 * x * y
 
     def init(x, y):
         return level - bath(x, y), _zeros_like(x), _zeros_like(x)
@@ -339,7 +331,7 @@ def graded_beach(n0: int = 2, N: int = 3, n_bands: int = 4) -> Workload:
     vx, vy, etov = graded_band_mesh(n0, n_bands)
 
     def bath(x, y):
-        return on_bed_grid(0.3 * (float(n_bands) - np.asarray(x, dtype=np.float64)))
+        return 0.3 * (float(n_bands) - np.asarray(x, dtype=np.float64))
 
     def init(x, y):
         x = np.asarray(x, dtype=np.float64)
@@ -351,6 +343,51 @@ def graded_beach(n0: int = 2, N: int = 3, n_bands: int = 4) -> Workload:
     return Workload("graded_beach", N, [Instance(vx, vy, etov, bath, init, "graded_beach")],
                     steps=10, cfl=0.3, max_levels=n_bands, seed=0,
                     notes=f"graded bands n0={n0}, N={N}, B=0.3(4-x), still level 0.55, hump at (2.3, 0.5)")
+
+
+def stepped_bed(case: str = "lake", n: int = 8, N: int = 3, seed: int = 13,
+                steps: int = 200) -> Workload:
+    """A bed that jumps across every face: on a jittered n x n x 2 unit square,
+    element k's bed is 0.1 x + 0.04 r_k (r_k ~ U[-1, 1] per element, drawn from
+    the seed) plus a step of height ``step`` on the elements whose first
+    vertex lies at x > 0.5.  The bathymetry function takes nodal arrays of
+    shape (K, Np) in element order (row k = element k), which is how both the
+    oracle and the library present their nodes.
+
+    * ``lake``:  still level 1.0 over a step of 0.3, fully wet (the discrete
+      steady state that hydrostatic reconstruction, Eq. 5.1-5.2, keeps);
+    * ``dam``:   the same bed, surface 1.1 for x < 0.3 and 1.0 beyond, at rest;
+    * ``ledge``: a step of 0.6 under still level 0.5 with a hump 0.1
+      exp(-50 r^2) at (0.4, 0.5): the elements beyond the step are dry and
+      their bed rises above the wet neighbours' surface."""
+    rng = np.random.default_rng(seed)
+    vx, vy, etov = structured_mesh(n, n, 0.0, 1.0, 0.0, 1.0, jitter=0.2, rng=rng)
+    K = etov.shape[0]
+    r = rng.uniform(-1.0, 1.0, size=K)
+    step = {"lake": 0.3, "dam": 0.3, "ledge": 0.6}[case]
+    on_step = vx[etov[:, 0]] > 0.5
+
+    def bath(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        if x.ndim != 2 or x.shape[0] != K:
+            raise ValueError("stepped_bed bathymetry takes (K, Np) nodal arrays in element order")
+        return 0.1 * x + (0.04 * r + step * on_step)[:, None]
+
+    def init(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        if case == "lake":
+            eta = np.ones_like(x)
+        elif case == "dam":
+            eta = np.where(x < 0.3, 1.1, 1.0)
+        else:
+            eta = 0.5 + 0.1 * np.exp(-50.0 * ((x - 0.4) ** 2 + (y - 0.5) ** 2))
+        h = np.maximum(0.0, eta - bath(x, y))
+        return h, _zeros_like(x), _zeros_like(x)
+
+    return Workload(f"stepped_{case}", N, [Instance(vx, vy, etov, bath, init, f"stepped_{case}")],
+                    steps=steps, cfl=0.2, seed=seed,
+                    notes=f"stepped bed ({case}) {n}x{n}x2 jittered, N={N}, jump on every face")
 
 
 def skewed_patch(N: int = 2) -> Workload:
@@ -448,7 +485,7 @@ def shoreline_lake(n: int = 16, N: int = 2, steps: int = 600) -> Workload:
     def bath(x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        return on_bed_grid(0.1 * (x * x + y * y))
+        return 0.1 * (x * x + y * y)
 
     def init(x, y):
         h = np.maximum(0.0, 0.1 - bath(x, y))
@@ -481,7 +518,7 @@ def parabolic_bowl(n: int = 16, N: int = 2, t_end_periods: float = 0.25) -> Work
     def bath(x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        return on_bed_grid(alpha * (x * x + y * y))
+        return alpha * (x * x + y * y)
 
     def exact(x, y, t):
         x = np.asarray(x, dtype=np.float64)
@@ -545,7 +582,7 @@ def oscillating_lake(n: int = 16, N: int = 2, t_end_periods: float = 1.0) -> Wor
     def bath(x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        return on_bed_grid(h0 * (x * x + y * y) / (a * a))
+        return h0 * (x * x + y * y) / (a * a)
 
     def exact(x, y, t):
         x = np.asarray(x, dtype=np.float64)
