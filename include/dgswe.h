@@ -228,6 +228,21 @@ typedef struct dg_diag {
 /* Deterministic FP64 reductions over instance `inst`.  Synchronises `stream`. */
 int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops): the reductions of dg_get_diagnostics, enqueued on `stream`
+ * without allocating, synchronising or copying to the host.  Writes 9 doubles
+ * to device memory `out_device` (8-byte aligned, caller-owned): mass,
+ * min_depth, pp_counts[3], tvb_counts[4] (counts as doubles), equal to the
+ * fields of dg_get_diagnostics for the same state.  The per-block partial
+ * sums go to a fixed device array of the library (256 x 16 doubles, 32 KiB,
+ * held on each device it runs on until the process ends); their count does
+ * not depend on the element count, so every solver size fits.  Calls that
+ * overlap on one device share that array and race.  The state buffers are the
+ * ones the schedule points to when the call is made.  Errors: DG_EINVAL (bad
+ * argument, misaligned out_device), DG_ENOTBOUND (no state yet), DG_EDEVICE
+ * (launch or symbol lookup failed). */
+int32_t dg_get_diagnostics_noalloc(dg_solver* h, int32_t inst, double* out_device, void* stream);
+
 /* Checkpoint: the full time-stepping state (states, RHS history, half-step
  * traces, counters) as an opaque byte blob; dg_checkpoint_bytes gives the
  * size: a 256-byte header (solver shape, the multi-rate schedule state, the

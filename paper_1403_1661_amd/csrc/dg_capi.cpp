@@ -1195,6 +1195,18 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
     return DG_OK;
 }
 
+int32_t dg_get_diagnostics_noalloc(dg_solver* h, int32_t inst, double* out_device, void* stream) {
+    if (!h || !out_device || inst < 0 || inst >= int(h->inst.size())) return fail(DG_EINVAL, "bad argument");
+    if (!h->prepared) return fail(DG_ENOTBOUND, "no state on the device yet");
+    if ((reinterpret_cast<uintptr_t>(out_device) & 7) != 0) return fail(DG_EINVAL, "out_device must be 8-byte aligned");
+    // the partial sums have a fixed count (the reduction's block count) that
+    // the device array holds whatever the element count
+    if (diag_scratch_doubles() < 256 * 16) return fail(DG_EINVAL, "reduction partials exceed the scratch array");
+    const DiagArgs a = diag_args(h, inst);
+    if (launch_diag_static(a, out_device, stream)) return fail(DG_EDEVICE, device_error_string());
+    return DG_OK;
+}
+
 // checkpoint blob: a 256-byte header (solver shape, per-level schedule
 // state, step and tick counts), one 32-byte record per instance (datum of the
 // stored levels, time step, initial wave speed, hash of the FP64 bed), then

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <mutex>
 
 #include "dg_launch.hpp"
 
@@ -1540,6 +1541,59 @@ int launch_tvb(const TvbArgs& a, void* stream, void* ev_start, void* ev_stop) {
     else
         hipLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a);
     return check_launch("tvb kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free diagnostics: the per-block partial sums of the reduction go
+// to a fixed device array instead of the bound workspace.  Its size does not
+// depend on the input (the partial kernel always runs kDiagBlocks blocks of
+// 16 values); every call on a device shares that device's copy.
+// ---------------------------------------------------------------------------
+constexpr int kScratchDoubles = kDiagBlocks * 16;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch`, looked up once per device
+// with the device current (the host-side name of the array is not a device
+// address)
+static int scratch_on_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        std::snprintf(g_dev_err, sizeof(g_dev_err), "hipGetDevice: %s", hipGetErrorString(e));
+        return -1;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        std::snprintf(g_dev_err, sizeof(g_dev_err), "device %d beyond the scratch table (%d)", dev, kMaxDevices);
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            std::snprintf(g_dev_err, sizeof(g_dev_err), "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return -1;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+int diag_scratch_doubles() { return kScratchDoubles; }
+
+int launch_diag_static(const DiagArgs& args, double* out, void* stream) {
+    static_assert(kDiagBlocks * 16 <= kScratchDoubles, "diagnostics partials exceed the scratch array");
+    double* part = nullptr;
+    if (scratch_on_current_device(&part)) return -1;
+    DiagArgs a = args;
+    a.partial = part;   // every slot is written by the partial kernel: nothing to clear
+    a.out = out;
+    return launch_diag(a, stream);
 }
 
 int launch_diag(const DiagArgs& a, void* stream) {

@@ -148,6 +148,10 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
                 void* ev_stop = nullptr);
 int launch_tvb(const TvbArgs& a, void* stream, void* ev_start = nullptr, void* ev_stop = nullptr);
 int launch_diag(const DiagArgs& a, void* stream);
+// the same reduction with its partial sums in a fixed device array (no
+// workspace, no allocation), results (9 doubles) written to `out` on the device
+int launch_diag_static(const DiagArgs& a, double* out, void* stream);
+int diag_scratch_doubles();
 // elements per block: matrix-core kernel 1, 2 or 4 waves of 64 / lanes
 // elements (N = 1, 2, 4: 4, 8, 16; N = 3: 5, 10, 20; N = 5: 3, 6, 12),
 // default 4 waves; VALU kernel floor(256 / Np) (fixed)

@@ -32,7 +32,7 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_destroy", "dg_last_error", "dg_
            "dg_advance", "dg_get_state", "dg_get_connectivity", "dg_get_levels",
            "dg_get_tvb_stencil", "dg_get_flags", "dg_get_diagnostics", "dg_checkpoint_bytes",
            "dg_get_checkpoint", "dg_set_checkpoint", "dg_set_profiling", "dg_kernel_timing",
-           "dg_autotune", "dg_capture_graph"]
+           "dg_autotune", "dg_capture_graph", "dg_get_diagnostics_noalloc"]
 
 
 class DGError(RuntimeError):
@@ -109,6 +109,7 @@ def load_library(path: Optional[str] = None):
         "dg_set_profiling": (_I32, [_P, _I32]),
         "dg_kernel_timing": (_I32, [_P, _I32, _D, C.POINTER(_I64), C.POINTER(_I64)]),
         "dg_capture_graph": (_I32, [_P, _P]),
+        "dg_get_diagnostics_noalloc": (_I32, [_P, _I32, _P, _P]),
         "dg_autotune": (_I32, [_P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _D, _P]),
     }
     for name, (res, args) in sig.items():
@@ -305,6 +306,12 @@ class Solver:
         return {"mass": d.mass, "min_depth": d.min_depth, "time": d.time, "steps": d.steps,
                 "negative_means": d.negative_means, "pp_counts": list(d.pp_counts),
                 "tvb_counts": list(d.tvb_counts)}
+
+    def diagnostics_noalloc(self, inst, out_device_ptr: int, stream=None):
+        """Enqueue the diagnostics reductions into 9 doubles at a device
+        address (mass, min depth, positivity and TVB code counts)."""
+        _check(self.lib.dg_get_diagnostics_noalloc(self.h, inst, C.c_void_p(out_device_ptr),
+                                                   C.c_void_p(self._stream(stream))))
 
     def checkpoint(self, stream=None) -> bytes:
         n = _I64()
