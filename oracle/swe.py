@@ -51,6 +51,7 @@ from typing import Callable, Optional
 import numpy as np
 
 from .mesh import Mesh, assign_levels, build_mesh, time_step, tvb_stencil, wave_speed
+from .overint import gauss_exterior_map, overint_operators
 from .refelem import reference_element
 
 AB_COEFFS = {1: (1.0,), 2: (1.5, -0.5), 3: (23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0)}
@@ -76,6 +77,7 @@ class Params:
     dry_literal: bool = False  # literal dry branch h = h0 instead of max(hbar, 0)
     thin_cut: float = 0.0      # > 0: momentum zeroed after the limiters where h < thin_cut
     max_levels: int = 1
+    overint: bool = False      # weak form with cubature and Gauss rules (Section 3, Section 7)
 
 
 @dataclass
@@ -141,6 +143,9 @@ class Solver:
         self.levels = assign_levels(self.mesh, self.p.max_levels)
         self.stencil = tvb_stencil(self.mesh)
         self.ghost = ghost
+        if self.p.overint:
+            self.oi = overint_operators(self.ref)
+            self.gmapP = gauss_exterior_map(self.mesh, self.oi.NG)
         self.t = 0.0
         self.q = None
         self.B = None
@@ -226,6 +231,81 @@ class Solver:
         return qM, qP, BM, BP, nx, ny
 
     def rhs(self, q, B, t=0.0, qP_override=None):
+        if self.p.overint:
+            return self.rhs_overint(q, B, t, qP_override)
+        return self.rhs_nodal(q, B, t, qP_override)
+
+    def rhs_overint(self, q, B, t=0.0, qP_override=None):
+        """Weak form with over-integration (Section 3, Eq. 3.2; Section 7,
+        Volume and Surface kernels): N = Pr cF1 + Ps cF2 + P cS at the
+        cubature nodes with the plain source cS = (0, -g h B_x, -g h B_y),
+        S = -L^g (Fscale Fn*) at the Gauss nodes of the faces with the
+        well-balanced flux of Eq. 5.1-5.2 (the wave speed maxed over the
+        face's Gauss points of both sides)."""
+        oi, m, p = self.oi, self.mesh, self.p
+        g = p.g
+        NG = oi.NG
+        # volume: interpolate to the cubature nodes
+        h, hu, hv = q @ oi.Ic.T
+        Bx = m.rx[:, None] * (B @ oi.Drc.T) + m.sx[:, None] * (B @ oi.Dsc.T)
+        By = m.ry[:, None] * (B @ oi.Drc.T) + m.sy[:, None] * (B @ oi.Dsc.T)
+        u, v = self.velocity(h, hu, hv)
+        F = np.stack([hu, hu * u + 0.5 * g * h * h, hu * v])
+        G = np.stack([hv, hv * u, hv * v + 0.5 * g * h * h])
+        cF1 = m.rx[:, None] * F + m.ry[:, None] * G
+        cF2 = m.sx[:, None] * F + m.sy[:, None] * G
+        cS = np.stack([np.zeros_like(h), -g * h * Bx, -g * h * By])
+        R = cF1 @ oi.Pr.T + cF2 @ oi.Ps.T + cS @ oi.P.T
+        # faces: traces at the Gauss nodes
+        qM = q @ oi.Ig.T                          # (3, K, 3 NG)
+        BM = B @ oi.Ig.T
+        src = qM if qP_override is None else qP_override @ oi.Ig.T
+        qP = src.reshape(3, -1)[:, self.gmapP]
+        BP = BM.reshape(-1)[self.gmapP]
+        nx = np.repeat(m.nx, NG, axis=1)
+        ny = np.repeat(m.ny, NG, axis=1)
+        wall = np.repeat(m.wall, NG, axis=1)
+        if self.ghost is None:
+            mn = qM[1] * nx + qM[2] * ny
+            ghost = np.stack([qM[0], qM[1] - 2.0 * mn * nx, qM[2] - 2.0 * mn * ny])
+        else:
+            gh, ghu, ghv = self.ghost(m.x @ oi.Ig.T, m.y @ oi.Ig.T, t)
+            ghost = np.stack([gh, ghu, ghv])
+        qP = np.where(wall[None], ghost, qP)
+        BP = np.where(wall, BM, BP)
+        fstar = self._wb_flux(qM, qP, BM, BP, nx, ny, NG)
+        fs = np.repeat(m.fscale, NG, axis=1)
+        R -= (fs * fstar) @ oi.Lg.T
+        return R
+
+    def _wb_flux(self, qM, qP, BM, BP, nx, ny, npf):
+        """Well-balanced Lax-Friedrichs flux F*.n of Eq. 5.1-5.2 at face
+        points, npf points per face (wave speed maxed over each face)."""
+        g = self.p.g
+        hM, huM, hvM = qM
+        hP, huP, hvP = qP
+        uM, vM = self.velocity(hM, huM, hvM)
+        uP, vP = self.velocity(hP, huP, hvP)
+        Bmax = np.maximum(BM, BP)
+        hsM = np.maximum(0.0, hM + BM - Bmax)
+        hsP = np.maximum(0.0, hP + BP - Bmax)
+        unM = uM * nx + vM * ny
+        unP = uP * nx + vP * ny
+        lam = np.maximum(np.abs(unM) + np.sqrt(g * hsM), np.abs(unP) + np.sqrt(g * hsP))
+        lam = np.repeat(lam.reshape(self.K, 3, npf).max(axis=2), npf, axis=1)
+        qsM = np.stack([hsM, hsM * uM, hsM * vM])
+        qsP = np.stack([hsP, hsP * uP, hsP * vP])
+
+        def flux_n(hs, u, v, un):
+            return np.stack([hs * un,
+                             hs * u * un + 0.5 * g * hs * hs * nx,
+                             hs * v * un + 0.5 * g * hs * hs * ny])
+
+        f_lf = 0.5 * (flux_n(hsM, uM, vM, unM) + flux_n(hsP, uP, vP, unP)) - 0.5 * lam * (qsP - qsM)
+        corr = 0.5 * g * (hM * hM - hsM * hsM)
+        return f_lf + np.stack([np.zeros_like(corr), corr * nx, corr * ny])
+
+    def rhs_nodal(self, q, B, t=0.0, qP_override=None):
         ref, m, p = self.ref, self.mesh, self.p
         g = p.g
         h, hu, hv = q
