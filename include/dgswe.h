@@ -117,6 +117,12 @@ typedef struct dg_params {
     double thin_cut;        /* >= 0; > 0: after the limiters, momentum is set to zero */
                             /* at nodes whose depth is below thin_cut (thin films at  */
                             /* shorelines; the paper is silent there).  0 = off       */
+    int32_t overint;        /* 0: nodal collocation (strong form, Dr/Ds and LIFT on   */
+                            /* the nodes); 1: the weak form of Eq. 3.2 with volume    */
+                            /* integrals by cubature and face integrals by Gauss      */
+                            /* quadrature, both exact to degree 3N (Section 3 and the */
+                            /* Volume/Surface kernels of Section 7): N <= 5, on the   */
+                            /* vector-ALU paths DG_PLAIN_FP32 and DG_FUSED_FP32        */
 } dg_params;
 
 /* Fill *p with the defaults: g 9.81, cfl 0.5, h0 = eps = 1e-5, hvel 1e-3, M 10, nu 1.5,
@@ -155,7 +161,12 @@ int32_t dg_node_coords(const dg_solver* h, int32_t inst, double* x, double* y);
 /* Reference nodes r, s (Np each) and operators, row-major, FP64:
  * which = 0: Dr (Np x Np), 1: Ds (Np x Np), 2: LIFT (Np x 3Nfp),
  * 3: mass matrix (Np x Np), 4: cell-integral weights w (Np),
- * 5: face node indices (3 x Nfp, as doubles). */
+ * 5: face node indices (3 x Nfp, as doubles).
+ * Over-integrated weak form (any solver; q = (3N+2)/2, Ncub = q^2, NG = q):
+ * 6: cubature nodes and weights (3 x Ncub: r, s, w), 7: basis at the
+ * cubature nodes Ic (Ncub x Np), 8: Pr, 9: Ps, 10: P (Np x Ncub each),
+ * 11: Gauss points and weights on [-1, 1] (2 x NG), 12: face-node basis at the
+ * Gauss points I1 (NG x Nfp), 13: L^g (Np x 3NG).  DG_EINVAL for other ids. */
 int32_t dg_reference(const dg_solver* h, int32_t which, double* out);
 int32_t dg_reference_nodes(const dg_solver* h, double* r, double* s);
 

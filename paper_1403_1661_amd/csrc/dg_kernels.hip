@@ -509,6 +509,247 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     reinterpret_cast<short*>(Qo + 3 * KNp)[idx] = lo_encode(out[0], olo);
 }
 
+
+// ---------------------------------------------------------------------------
+// right-hand side of the over-integrated weak form (Section 3, Eq. 3.2 with
+// cubature and Gauss rules; Section 7, Volume and Surface kernels):
+//   R = Pr cF1 + Ps cF2 + P cS - L^g (Fscale Fn*)
+// with cF1 = rx F + ry G, cF2 = sx F + sy G and cS at the Ncub cubature
+// nodes and Fn* at the 3 NG Gauss nodes of the faces.  The pressure and the
+// bed source are taken in perturbation form about the element's first-node
+// level eta_k (d = eta - eta_k): volume pressure (g/2) d (2h - d), source
+// -g d grad B, and on the faces the flux minus (g/2)(eta_k - B-)^2 n, i.e.
+// (g/2) d- (2h- - d-) + (g/4)(h*+ - h*-)(h*+ + h*-) in the momentum flux.
+// Under rules exact to degree 3N this differs from the plain form (pressure
+// (g/2) h^2, source -g h grad B) only by that face term, which it carries, so
+// both are the same scheme; still water gives d = 0 and a zero jump exactly.
+// Element data are interpolated as d, h, hu, hv (and the bed slope from the
+// nodes) so that every term of still water is zero in any precision.
+// One block = E elements, W = max(Ncub, Np, 3 NG) lanes per element.
+// ---------------------------------------------------------------------------
+template <int N>
+struct OShape {
+    static constexpr int Np = (N + 1) * (N + 2) / 2;
+    static constexpr int Nfp = N + 1;
+    static constexpr int nF = 3 * (N + 1);
+    static constexpr int Q = overint_points(N);
+    static constexpr int NC = Q * Q;
+    static constexpr int NG = Q;
+    static constexpr int NGF = 3 * Q;
+    static constexpr int W0 = NC > Np ? NC : Np;
+    static constexpr int W = W0 > NGF ? W0 : NGF;
+    static constexpr int E = 256 / W;
+};
+
+template <int N>
+__global__ void __launch_bounds__(256) rhs_overint_kernel(StepArgs a) {
+    using S = OShape<N>;
+    constexpr int Np = S::Np, Nfp = S::Nfp, nF = S::nF, NC = S::NC, NG = S::NG, NGF = S::NGF;
+    constexpr int W = S::W, E = S::E;
+    __shared__ float sIc[NC * Np], sPr[Np * NC], sPs[Np * NC], sP[Np * NC], sLg[Np * NGF], sI1[NG * Nfp];
+    __shared__ float sN[6][E][Np];      // h, d, hu, hv, dB/dx, dB/dy at the nodes
+    __shared__ float sT[5][E][nF];      // exterior h, hu, hv, d (about the own eta_k), B+ - B- at own face nodes
+    __shared__ float sC[8][E][NC];      // cF1 (3), cF2 (3), cS (hu, hv) at the cubature nodes
+    __shared__ float sF[3][E][NGF];     // Fscale Fn* at the Gauss nodes
+    __shared__ float sLam[E][NGF];
+
+    const int tid = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int k0 = a.k_begin + blk * E;
+    for (int t = tid; t < NC * Np; t += 256) {
+        sIc[t] = a.ops.oIc[t];
+        sPr[t] = a.ops.oPr[t];
+        sPs[t] = a.ops.oPs[t];
+        sP[t] = a.ops.oP[t];
+    }
+    for (int t = tid; t < Np * NGF; t += 256) sLg[t] = a.ops.oLg[t];
+    for (int t = tid; t < NG * Nfp; t += 256) sI1[t] = a.ops.oI1[t];
+
+    const int e = tid / W;
+    const int i = tid - e * W;
+    const int k = k0 + e;
+    const bool live = e < E && k < a.k_end;
+    const long long KNp = a.KNp;
+    const float g = a.g, hvel = a.hvel;
+    // ---- nodal data of the element (lanes i < Np)
+    float etak = 0.f, lok = 0.f;
+    LevelArgs L = a.lev[0];
+    if (live) {
+        L = pick_level(a, level_of(a, k));
+        const float* Q = a.Q[L.parity];
+        const long long b0 = (long long)k * Np;
+        etak = Q[b0];
+        lok = lo_decode(etak, reinterpret_cast<const short*>(Q + 3 * KNp)[b0]);
+        if (i < Np) {
+            const long long idx = b0 + i;
+            const float eta = Q[idx];
+            const float lo = lo_decode(eta, reinterpret_cast<const short*>(Q + 3 * KNp)[idx]);
+            const float Bn = a.B[idx];
+            const float bl = lo_decode(Bn, a.Blo[idx]);
+            sN[0][e][i] = (eta - Bn) + (lo - bl);
+            sN[1][e][i] = (eta - etak) + (lo - lok);
+            sN[2][e][i] = Q[KNp + idx];
+            sN[3][e][i] = Q[2 * KNp + idx];
+            sN[4][e][i] = a.dB[idx];
+            sN[5][e][i] = a.dB[KNp + idx];
+        }
+    }
+    // ---- exterior values at the own face nodes (lanes i < 3 (N+1))
+    if (live && i < nF) {
+        const int f = i / Nfp, j = i - f * Nfp;
+        const int4 cn = reinterpret_cast<const int4*>(a.conn)[k];
+        const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
+        if (nb >= 0) {
+            const int f2 = (cn.w >> (2 * f)) & 3;
+            const int l2 = level_of(a, nb);
+            const LevelArgs L2 = pick_level(a, l2);
+            const long long id2 = (long long)nb * Np + a.ops.fmask[f2 * Nfp + (Nfp - 1 - j)];
+            const float BP = a.B[id2];
+            const float blP = lo_decode(BP, a.Blo[id2]);
+            const long long idM = (long long)k * Np + a.ops.fmask[i];
+            const float BM = a.B[idM];
+            const float blM = lo_decode(BM, a.Blo[idM]);
+            float etaP, loP = 0.f, huP, hvP;
+            if (L2.active || a.half == nullptr) {
+                const float* Q2 = a.Q[L2.parity];
+                etaP = Q2[id2];
+                huP = Q2[KNp + id2];
+                hvP = Q2[2 * KNp + id2];
+                loP = lo_decode(etaP, reinterpret_cast<const short*>(Q2 + 3 * KNp)[id2]);
+            } else {
+                const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - j);
+                etaP = a.half[hid];
+                huP = a.half[a.KnF + hid];
+                hvP = a.half[2 * a.KnF + hid];
+            }
+            sT[0][e][i] = (etaP - BP) + (loP - blP);
+            sT[1][e][i] = huP;
+            sT[2][e][i] = hvP;
+            sT[3][e][i] = (etaP - etak) + (loP - lok);
+            sT[4][e][i] = (BP - BM) + (blP - blM);
+        }
+    }
+    __syncthreads();
+    if (live && i < nF) {
+        const int f = i / Nfp;
+        const int4 cn = reinterpret_cast<const int4*>(a.conn)[k];
+        const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
+        if (nb < 0) {   // reflective wall: the mirror state, same bed
+            const int n = a.ops.fmask[i];
+            const float* gk = a.geo + 16LL * k;
+            const float nx = gk[4 + f], ny = gk[7 + f];
+            const float huM = sN[2][e][n], hvM = sN[3][e][n];
+            const float mn = huM * nx + hvM * ny;
+            sT[0][e][i] = sN[0][e][n];
+            sT[1][e][i] = huM - 2.f * mn * nx;
+            sT[2][e][i] = hvM - 2.f * mn * ny;
+            sT[3][e][i] = sN[1][e][n];
+            sT[4][e][i] = 0.f;
+        }
+    }
+    // ---- volume fluxes and source at the cubature nodes (lanes i < Ncub)
+    if (live && i < NC) {
+        float h = 0.f, d = 0.f, hu = 0.f, hv = 0.f, bx = 0.f, by = 0.f;
+#pragma unroll
+        for (int n = 0; n < Np; ++n) {
+            const float c = sIc[i * Np + n];
+            h += c * sN[0][e][n];
+            d += c * sN[1][e][n];
+            hu += c * sN[2][e][n];
+            hv += c * sN[3][e][n];
+            bx += c * sN[4][e][n];
+            by += c * sN[5][e][n];
+        }
+        const float4 g0 = reinterpret_cast<const float4*>(a.geo)[4LL * k];   // rx, ry, sx, sy
+        const float fv = vel_factor(h, hvel);
+        const float u = hu * fv, v = hv * fv;
+        const float p = 0.5f * g * (d * (2.f * h - d));
+        const float F[3] = {hu, hu * u + p, hu * v};
+        const float G[3] = {hv, hv * u, hv * v + p};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sC[c][e][i] = g0.x * F[c] + g0.y * G[c];
+            sC[3 + c][e][i] = g0.z * F[c] + g0.w * G[c];
+        }
+        sC[6][e][i] = -g * d * bx;
+        sC[7][e][i] = -g * d * by;
+    }
+    __syncthreads();
+    // ---- numerical flux at the Gauss nodes (lanes i < 3 NG)
+    float hsM = 0.f, hsP = 0.f, uM = 0.f, vM = 0.f, uP = 0.f, vP = 0.f, jump = 0.f;
+    float hM = 0.f, dM = 0.f, huM = 0.f, hvM = 0.f, huP = 0.f, hvP = 0.f, nx = 0.f, ny = 0.f, fs = 0.f;
+    if (live && i < NGF) {
+        const int f = i / NG, gq = i - f * NG;
+        float hP = 0.f, dP = 0.f, dB = 0.f;
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j) {
+            const float c = sI1[gq * Nfp + j];
+            const int n = a.ops.fmask[f * Nfp + j];
+            const int t = f * Nfp + j;
+            hM += c * sN[0][e][n];
+            dM += c * sN[1][e][n];
+            huM += c * sN[2][e][n];
+            hvM += c * sN[3][e][n];
+            hP += c * sT[0][e][t];
+            huP += c * sT[1][e][t];
+            hvP += c * sT[2][e][t];
+            dP += c * sT[3][e][t];
+            dB += c * sT[4][e][t];
+        }
+        const float* gk = a.geo + 16LL * k;
+        nx = gk[4 + f];
+        ny = gk[7 + f];
+        fs = gk[10 + f];
+        // Eq. 5.1 with max(B-, B+) - B- = max(0, dB), max(B-, B+) - B+ = max(0, -dB)
+        hsM = fmaxf(0.f, hM - fmaxf(0.f, dB));
+        hsP = fmaxf(0.f, hP - fmaxf(0.f, -dB));
+        // both sides wet: h*+ - h*- = eta+ - eta-, formed from the levels
+        jump = (hsM > 0.f && hsP > 0.f) ? dP - dM : hsP - hsM;
+        const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
+        uM = huM * fM;
+        vM = hvM * fM;
+        uP = huP * fP;
+        vP = hvP * fP;
+        const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
+        sLam[e][i] = fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP));
+    }
+    __syncthreads();
+    if (live && i < NGF) {
+        const int f = i / NG;
+        float lam = sLam[e][f * NG];
+#pragma unroll
+        for (int t = 1; t < NG; ++t) lam = fmaxf(lam, sLam[e][f * NG + t]);
+        const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
+        const float pc = 0.5f * g * (dM * (2.f * hM - dM)) + 0.25f * g * jump * (hsP + hsM);
+        sF[0][e][i] = fs * (0.5f * (hsM * unM + hsP * unP) - 0.5f * lam * jump);
+        sF[1][e][i] = fs * (0.5f * (hsM * uM * unM + hsP * uP * unP) + pc * nx - 0.5f * lam * (hsP * uP - hsM * uM));
+        sF[2][e][i] = fs * (0.5f * (hsM * vM * unM + hsP * vP * unP) + pc * ny - 0.5f * lam * (hsP * vP - hsM * vM));
+    }
+    __syncthreads();
+    // ---- projection to the nodes (lanes i < Np)
+    if (!live || i >= Np) return;
+    float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll 4
+    for (int c = 0; c < NC; ++c) {
+        const float pr = sPr[i * NC + c], ps = sPs[i * NC + c], pp = sP[i * NC + c];
+        r0 += pr * sC[0][e][c] + ps * sC[3][e][c];
+        r1 += pr * sC[1][e][c] + ps * sC[4][e][c] + pp * sC[6][e][c];
+        r2 += pr * sC[2][e][c] + ps * sC[5][e][c] + pp * sC[7][e][c];
+    }
+#pragma unroll
+    for (int t = 0; t < NGF; ++t) {
+        const float lg = sLg[i * NGF + t];
+        r0 -= lg * sF[0][e][t];
+        r1 -= lg * sF[1][e][t];
+        r2 -= lg * sF[2][e][t];
+    }
+    float* R0 = a.R[L.slot[0]];
+    const long long idx = (long long)k * Np + i;
+    R0[idx] = r0;
+    R0[KNp + idx] = r1;
+    R0[2 * KNp + idx] = r2;
+}
+
 // ---------------------------------------------------------------------------
 // characteristic rows L of the flux Jacobian in direction (ex, ey) at a cell
 // mean (Section 5.3, Cockburn-Shu), FP64
@@ -1527,6 +1768,30 @@ int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_s
         case 6: return launch_step_n<6>(a, s, epb, e0, e1);
         default:
             std::snprintf(g_dev_err, sizeof(g_dev_err), "unsupported N=%d", a.N);
+            return -1;
+    }
+}
+
+template <int N>
+static int launch_rhs_overint_n(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int n = a.k_end - a.k_begin;
+    if (n <= 0) return 0;
+    constexpr int E = OShape<N>::E;
+    dispatch(rhs_overint_kernel<N>, (n + E - 1) / E, 256, s, a, e0, e1);
+    return check_launch("over-integrated rhs kernel");
+}
+
+int launch_rhs_overint(const StepArgs& a, void* stream, void* ev_start, void* ev_stop) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = static_cast<hipEvent_t>(ev_start), e1 = static_cast<hipEvent_t>(ev_stop);
+    switch (a.N) {
+        case 1: return launch_rhs_overint_n<1>(a, s, e0, e1);
+        case 2: return launch_rhs_overint_n<2>(a, s, e0, e1);
+        case 3: return launch_rhs_overint_n<3>(a, s, e0, e1);
+        case 4: return launch_rhs_overint_n<4>(a, s, e0, e1);
+        case 5: return launch_rhs_overint_n<5>(a, s, e0, e1);
+        default:
+            std::snprintf(g_dev_err, sizeof(g_dev_err), "over-integration supports N <= 5, got N=%d", a.N);
             return -1;
     }
 }

@@ -61,7 +61,19 @@ struct DevOps {
     const double* pmid;    // 3 x Np: P1 midpoint value minus mean
     const double* phi;     // 3 x Np: midpoint-Lagrange P1 basis at the nodes
     const double* Wred;    // FP64 MFMA A-operand of [w/2; P1 midpoint - mean] (4 x 64)
+    // over-integrated weak form (FP32): Ic [Ncub][Np], Pr, Ps, P [Np][Ncub],
+    // Lg [Np][3 NG], I1 [NG][Nfp] (see overint_points)
+    const float* oIc;
+    const float* oPr;
+    const float* oPs;
+    const float* oP;
+    const float* oLg;
+    const float* oI1;
 };
+
+// points per direction of the over-integrated rules (exact to degree 3N):
+// Ncub = q^2 cubature nodes, q Gauss points per face
+constexpr int overint_points(int N) { return (3 * N + 2) / 2; }
 
 struct StepArgs {
     int N, mode, engine;
@@ -147,6 +159,9 @@ struct DiagArgs {
 int launch_step(const StepArgs& a, void* stream, int elems_per_block, void* ev_start = nullptr,
                 void* ev_stop = nullptr);
 int launch_tvb(const TvbArgs& a, void* stream, void* ev_start = nullptr, void* ev_stop = nullptr);
+// right-hand side of the over-integrated weak form into a.r_now (multi-rate:
+// the ring slot of each element's level), N <= 5
+int launch_rhs_overint(const StepArgs& a, void* stream, void* ev_start = nullptr, void* ev_stop = nullptr);
 int launch_diag(const DiagArgs& a, void* stream);
 // the same reduction with its partial sums in a fixed device array (no
 // workspace, no allocation), results (9 doubles) written to `out` on the device

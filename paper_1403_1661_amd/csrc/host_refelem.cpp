@@ -123,6 +123,36 @@ void mode_grad(double r, double s, int i, int j, double& dr, double& ds) {
     ds *= std::sqrt(2.0);
 }
 
+// Gauss points and weights of the weight (1-x)^a (1+x)^b on [-1, 1]: roots
+// of the orthonormal Jacobi polynomial of degree q by Newton iteration with
+// the roots already found divided out, weights from the Christoffel numbers
+// w_i = 1 / sum_{k<q} p_k(x_i)^2 of the orthonormal family.
+void gauss_jacobi(int q, double a, double b, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(q, 0.0);
+    w.assign(q, 0.0);
+    for (int i = 0; i < q; ++i) {
+        double t = -std::cos(M_PI * (i + 0.75) / (q + 0.5));
+        for (int it = 0; it < 200; ++it) {
+            const double f = jacobi(t, a, b, q), df = jacobi_deriv(t, a, b, q);
+            double defl = 0.0;
+            for (int j = 0; j < i; ++j) defl += 1.0 / (t - x[j]);
+            const double dt = f / (df - f * defl);
+            t -= dt;
+            if (std::fabs(dt) < 1e-16 * std::max(1.0, std::fabs(t))) break;
+        }
+        x[i] = t;
+    }
+    std::sort(x.begin(), x.end());
+    for (int i = 0; i < q; ++i) {
+        double sum = 0.0;
+        for (int k = 0; k < q; ++k) {
+            const double p = jacobi(x[i], a, b, k);
+            sum += p * p;
+        }
+        w[i] = 1.0 / sum;
+    }
+}
+
 }  // namespace
 
 std::vector<double> gauss_lobatto(int N) {
@@ -273,6 +303,72 @@ RefElement build_reference(int N) {
         for (int e = 0; e < 3; ++e) re.phi_mid(e, p) = 1.0 - 2.0 * lam[(e + 2) % 3];
     }
     return re;
+}
+
+OverInt build_overint(const RefElement& re) {
+    const int N = re.N, Np = re.Np, Nfp = re.Nfp;
+    OverInt oi;
+    oi.q = (3 * N + 2) / 2;
+    const int q = oi.q;
+    oi.Ncub = q * q;
+    oi.NG = q;
+    std::vector<double> xa, wa, xb, wb;
+    gauss_jacobi(q, 0.0, 0.0, xa, wa);
+    gauss_jacobi(q, 1.0, 0.0, xb, wb);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            oi.rc.push_back(0.5 * (1.0 + xa[i]) * (1.0 - xb[j]) - 1.0);
+            oi.sc.push_back(xb[j]);
+            oi.wc.push_back(0.5 * wa[i] * wb[j]);
+        }
+    oi.xg = xa;
+    oi.wg = wa;
+    std::vector<std::pair<int, int>> modes;
+    for (int i = 0; i <= N; ++i)
+        for (int j = 0; j <= N - i; ++j) modes.push_back({i, j});
+    Mat V(Np, Np);
+    for (int p = 0; p < Np; ++p)
+        for (int m = 0; m < Np; ++m) V(p, m) = mode(re.r[p], re.s[p], modes[m].first, modes[m].second);
+    const Mat Vinv = inverse(V);
+    const int Nc = oi.Ncub;
+    Mat Vc(Nc, Np), Vrc(Nc, Np), Vsc(Nc, Np);
+    for (int c = 0; c < Nc; ++c)
+        for (int m = 0; m < Np; ++m) {
+            Vc(c, m) = mode(oi.rc[c], oi.sc[c], modes[m].first, modes[m].second);
+            mode_grad(oi.rc[c], oi.sc[c], modes[m].first, modes[m].second, Vrc(c, m), Vsc(c, m));
+        }
+    oi.Ic = Vc * Vinv;
+    const Mat Drc = Vrc * Vinv, Dsc = Vsc * Vinv;
+    const Mat Minv = inverse(re.M);
+    Mat DrW = Drc.transpose(), DsW = Dsc.transpose(), IW = oi.Ic.transpose();   // Np x Nc
+    for (int i = 0; i < Np; ++i)
+        for (int c = 0; c < Nc; ++c) {
+            DrW(i, c) *= oi.wc[c];
+            DsW(i, c) *= oi.wc[c];
+            IW(i, c) *= oi.wc[c];
+        }
+    oi.Pr = Minv * DrW;
+    oi.Ps = Minv * DsW;
+    oi.P = Minv * IW;
+    // face-node Lagrange basis (GLL nodes) at the Gauss points, barycentric form
+    const std::vector<double> gll = gauss_lobatto(N);
+    std::vector<double> bw(Nfp, 1.0);
+    for (int j = 0; j < Nfp; ++j)
+        for (int k = 0; k < Nfp; ++k)
+            if (k != j) bw[j] /= (gll[j] - gll[k]);
+    oi.I1 = Mat(q, Nfp);
+    for (int g = 0; g < q; ++g) {
+        double den = 0.0;
+        for (int j = 0; j < Nfp; ++j) den += bw[j] / (oi.xg[g] - gll[j]);
+        for (int j = 0; j < Nfp; ++j) oi.I1(g, j) = bw[j] / (oi.xg[g] - gll[j]) / den;
+    }
+    // L^g = M^-1 E_g with E_g(node, f q + g) = sum_j I1(g, j) Wg(g) [node = fmask(f, j)]
+    Mat Eg(Np, 3 * q);
+    for (int f = 0; f < 3; ++f)
+        for (int g = 0; g < q; ++g)
+            for (int j = 0; j < Nfp; ++j) Eg(re.fmask[f * Nfp + j], f * q + g) += oi.I1(g, j) * oi.wg[g];
+    oi.Lg = Minv * Eg;
+    return oi;
 }
 
 }  // namespace dgswe

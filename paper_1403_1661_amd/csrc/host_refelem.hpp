@@ -45,7 +45,23 @@ struct RefElement {
     Mat phi_mid;                // 3 x Np: midpoint-Lagrange P1 basis at the nodes
 };
 
+// Over-integrated weak-form operators (the cubature and Gauss rules of the
+// paper's volume and surface integrals): rules exact to degree 3N with q =
+// ceil((3N+1)/2) points per direction (cubature: Stroud's conical product of
+// q Gauss-Legendre by q Gauss-Jacobi(1,0) points) and per face (Gauss-Legendre,
+// counter-clockwise along the face).
+struct OverInt {
+    int q = 0, Ncub = 0, NG = 0;
+    std::vector<double> rc, sc, wc;   // cubature nodes and weights (sum 2)
+    std::vector<double> xg, wg;       // Gauss points and weights on [-1, 1]
+    Mat Ic;                           // Ncub x Np: nodal basis at the cubature nodes
+    Mat Pr, Ps, P;                    // Np x Ncub: M^-1 Dr_c^T W, M^-1 Ds_c^T W, M^-1 Ic^T W
+    Mat I1;                           // NG x Nfp: face-node Lagrange basis at the Gauss points
+    Mat Lg;                           // Np x 3NG: M^-1 [I_g0^T Wg, I_g1^T Wg, I_g2^T Wg]
+};
+
 std::vector<double> gauss_lobatto(int N);
 RefElement build_reference(int N);
+OverInt build_overint(const RefElement& re);
 
 }  // namespace dgswe

@@ -52,7 +52,7 @@ class Params(C.Structure):
                 ("eps", C.c_double), ("hvel", C.c_double), ("tvb_M", C.c_double), ("tvb_nu", C.c_double),
                 ("limiter_mask", C.c_int32), ("max_levels", C.c_int32),
                 ("precision", C.c_int32), ("dry_literal", C.c_int32), ("use_graph", C.c_int32),
-                ("elems_per_block", C.c_int32), ("thin_cut", C.c_double)]
+                ("elems_per_block", C.c_int32), ("thin_cut", C.c_double), ("overint", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -224,8 +224,12 @@ class Solver:
         return x, y
 
     def reference(self, which: int):
+        q = (3 * self.N + 2) // 2
+        nc = q * q
         shapes = {0: (self.Np, self.Np), 1: (self.Np, self.Np), 2: (self.Np, 3 * self.Nfp),
-                  3: (self.Np, self.Np), 4: (self.Np,), 5: (3, self.Nfp)}
+                  3: (self.Np, self.Np), 4: (self.Np,), 5: (3, self.Nfp), 6: (3, nc), 7: (nc, self.Np),
+                  8: (self.Np, nc), 9: (self.Np, nc), 10: (self.Np, nc), 11: (2, q), 12: (q, self.Nfp),
+                  13: (self.Np, 3 * q)}
         out = np.empty(shapes[which])
         _check(self.lib.dg_reference(self.h, which, _dptr(out)))
         return out

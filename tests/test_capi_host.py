@@ -44,6 +44,32 @@ def test_reference_element_matches_oracle(N):
     assert np.array_equal(s.reference(5).astype(int), ref.fmask)
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+def test_overint_operators_match_oracle(N):
+    """The library's cubature and Gauss rules and the over-integrated
+    operators (built on the host by its own Gauss-Jacobi Newton iteration and
+    barycentric face interpolation) agree with the oracle's (SciPy rules,
+    2D Vandermonde evaluation at the face points)."""
+    from oracle.overint import overint_operators
+    vx, vy, etov = W.structured_mesh(2, 2, 0, 1, 0, 1)
+    s = dgswe.Solver([(vx, vy, etov)], N)
+    oi = overint_operators(reference_element(N))
+    cub = s.reference(6)
+    assert np.max(np.abs(cub[0] - oi.rc)) < 1e-14 and np.max(np.abs(cub[1] - oi.sc)) < 1e-14
+    assert np.max(np.abs(cub[2] - oi.wc)) < 1e-15
+    gw = s.reference(11)
+    xi = np.polynomial.legendre.leggauss(oi.NG)[0]
+    assert np.max(np.abs(gw[0] - xi)) < 1e-14 and np.max(np.abs(gw[1] - oi.wg)) < 1e-14
+    for which, want in ((7, oi.Ic), (8, oi.Pr), (9, oi.Ps), (10, oi.P), (13, oi.Lg)):
+        got = s.reference(which)
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) < 1e-11 * max(1.0, np.max(np.abs(want))), which
+    # face-node interpolation at the Gauss points reproduces I_g on face 0
+    ref = reference_element(N)
+    I1 = s.reference(12)
+    assert np.max(np.abs(I1 - oi.Ig[:oi.NG][:, ref.fmask[0]])) < 1e-13
+
+
 @pytest.mark.parametrize("case", ["c1", "wetdry", "c3small", "barrier", "skewed"])
 def test_mesh_setup_matches_oracle(case):
     if case == "c1":
