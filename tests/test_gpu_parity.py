@@ -362,7 +362,15 @@ def test_multirate_wetdry(path, N):
     coarse steps = 80 ticks; the positivity limiter scales and dries elements
     of the active levels at every tick (Algorithm 5.1 applied level by
     level)."""
-    g, o, q = _compare(f"mrab-wetdry-N{N}", W.graded_beach(N=N), 10, precision=path, flip_frac=0.01)
+    # N = 1 puts a few thin-film elements (depth 1e-4 - 4e-4 against hvel =
+    # 1e-3) on the shoreline, where the momentum is conditioned at the FP32
+    # level: the FP64 oracle itself moves by up to 2.8e-6 after these 10 coarse
+    # steps when only its initial levels are perturbed by 6e-8 relative, once
+    # (tests/test_oracle_swe.py::test_graded_beach_shoreline_conditioning);
+    # FP32 storage re-rounds at each of the 80 ticks, so N = 1 is held to 2e-5
+    tol_m = 2e-5 if N == 1 else None
+    g, o, q = _compare(f"mrab-wetdry-N{N}", W.graded_beach(N=N), 10, precision=path, flip_frac=0.01,
+                       tol_m=tol_m)
     lev, _ = g.levels(0)
     assert np.array_equal(lev.astype(int), o.levels)
     d = g.diagnostics(0)

@@ -411,6 +411,35 @@ def test_mrab_wetdry_positivity_and_mass():
     assert s.flags.pp.max() == PP_DRY
 
 
+def test_graded_beach_shoreline_conditioning():
+    """How far the multi-rate wet/dry case at N = 1 (thin films on the
+    shoreline) is determined by its data: perturbing the initial surface
+    level by 6e-8 relative (the FP32 rounding of the stored level), once,
+    moves the FP64 momentum after 10 coarse steps by more than 1e-6 relative.
+    The GPU parity bound of that case rests on this figure."""
+    from helpers import rel_l2
+    wl = W.graded_beach(N=1)
+    ins = wl.instances[0]
+
+    def run(seed):
+        s = Solver(ins.vx, ins.vy, ins.etov, 1, Params(g=wl.g, cfl=wl.cfl, max_levels=wl.max_levels))
+        x, y = s.nodes()
+        B = s.interpolate(ins.bathymetry)
+        h, hu, hv = ins.initial(x, y)
+        if seed:
+            rng = np.random.default_rng(seed)
+            eta = 0.55 + (h + B - 0.55) * (1.0 + rng.uniform(-6e-8, 6e-8, h.shape))
+            h = np.where(h > 0.0, np.maximum(eta - B, 0.0), 0.0)
+        s.set_state(h, hu, hv, B)
+        s.run(10)
+        return s
+
+    a = run(0)
+    errs = [rel_l2(a, run(seed).q, a.q)["m"] for seed in (1, 2)]
+    assert max(errs) > 1e-6, errs
+    assert max(errs) < 1e-5, errs
+
+
 def test_pp_negative_mean_with_wet_nodes_is_dry():
     """At N = 4 the nodal mean weights of the three vertices are negative, so
     an element wet at its vertices and nearly dry elsewhere has every node
