@@ -110,13 +110,15 @@ def step_kernel_bytes(Np: int) -> int:
     return 64 * Np + 97
 
 
-def make_solver(wl, precision, use_graph=1, tune=False):
+def make_solver(wl, precision, use_graph=1, tune=False, overint=0):
     """Solver over all instances of the workload, state set and prepared;
     with tune, the launch shape of the step kernel is picked by the
-    library's autotuner (outside any timed region)."""
+    library's autotuner (outside any timed region).  overint: the
+    over-integrated weak form instead of nodal collocation."""
     from paper_1403_1661_amd import dgswe
     s = dgswe.Solver([(i.vx, i.vy, i.etov) for i in wl.instances], wl.N, g=wl.g, cfl=wl.cfl,
-                     precision=precision, use_graph=use_graph, max_levels=wl.max_levels)
+                     precision=precision, use_graph=use_graph, max_levels=wl.max_levels,
+                     overint=overint)
     s.bind("cuda:0")
     for j, ins in enumerate(wl.instances):
         x, y = s.node_coords(j)
@@ -261,9 +263,10 @@ def rel_l2_vs_golden(s, name):
 
 def accuracy_at_configured_steps(s, wl, name):
     """Run the solver on to the workload's configured step count and compare
-    with the stored oracle samples (None when already past it)."""
+    with the stored oracle samples (None when already past it or when no
+    samples are stored for this workload)."""
     left = wl.steps - s.steps_done
-    if left < 0:
+    if left < 0 or not os.path.exists(os.path.join(GOLDEN_DIR, f"{name}_oracle_samples.npz")):
         return None
     advance(s, left)
     return rel_l2_vs_golden(s, name)
@@ -373,6 +376,28 @@ def main():
             torch.cuda.empty_cache()
         plain = engines.get("plain_fp32")
 
+    # the paper's own discretisation: the over-integrated weak form (cubature
+    # volume term, Gauss surface term; N <= 5) on the vector-ALU kernels
+    overint = None
+    if not args.no_plain and wl.N <= 5:
+        e = make_solver(wl, "fused_fp32", use_graph=use_graph, tune=False, overint=1)
+        warm_and_capture(e, warmup, use_graph, torch)
+        te = timed(e, steps, torch)
+        e.set_profiling(True)
+        advance(e, prof_steps)
+        torch.cuda.synchronize()
+        rhs_us, _, _ = e.kernel_timing(0)
+        e.set_profiling(False)
+        overint = {"value": per_step * steps / te, "ms_per_step": 1e3 * te / steps,
+                   "rhs_kernel_avg_us": rhs_us,
+                   "note": "weak form with cubature and Gauss rules exact to degree 3N; RHS kernel "
+                           "then the vector-ALU update and limiters"}
+        if not args.no_accuracy:
+            overint["rel_l2_vs_oracle"] = accuracy_at_configured_steps(e, wl, f"{name}_overint")
+        progress(f"over-integrated: {overint['ms_per_step']:.4f} ms/step, RHS kernel {rhs_us:.1f} us")
+        del e
+        torch.cuda.empty_cache()
+
     kname = "step_mfma_kernel" if args.precision in ("fused_mfma32", "fused_bf16x3", "fused_bf16x6") \
         else "step_kernel"
     traffic = measured_traffic(name, args.precision, tuned)
@@ -409,6 +434,7 @@ def main():
         "plain_fp32": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "engines": engines,
+        "overint_fp32": overint,
         "rel_l2_vs_oracle": accuracy,
         "diagnostics": {"mass": sum(d["mass"] for d in diag), "min_depth": min(d["min_depth"] for d in diag),
                         "pp_counts": [sum(d["pp_counts"][c] for d in diag) for c in range(3)],

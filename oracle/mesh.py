@@ -172,6 +172,35 @@ def assign_levels(mesh: Mesh, max_levels: int) -> np.ndarray:
         lev = new
 
 
+def element_wave_speeds(mesh: Mesh, h, hu, hv, g: float, hvel: float) -> np.ndarray:
+    """Per-element wave speed for regrouping: the maximum of |(u,v)| + sqrt(g h)
+    (desingularised velocity) over the nodes of the element and of its face
+    neighbours (the speed that can enter it), floored at 1e-12."""
+    f = 2.0 * h / (h * h + np.maximum(h * h, hvel * hvel))
+    node = (np.hypot(hu * f, hv * f) + np.sqrt(g * np.maximum(h, 0.0))).max(axis=1)
+    return np.maximum(np.maximum(node, node[mesh.etoe].max(axis=1)), 1e-12)
+
+
+def speed_levels(mesh: Mesh, N: int, cfl: float, speeds: np.ndarray, max_levels: int):
+    """Levels from each element's own allowable step (Eq. 4.1 with a per
+    element): dt_k = CFL r_k / ((N+1)^2 a_k), dt_min = min dt_k, level l_k with
+    2^(l-1) dt_min <= dt_k < 2^l dt_min (tie tolerance 1e-12), capped at
+    max_levels, then the 2:1 rule across faces.  Returns (levels, dt_min)."""
+    dt = cfl * mesh.inradius / ((N + 1) ** 2 * speeds)
+    dtmin = float(dt.min())
+    lev = np.ones(mesh.K, dtype=np.int64)
+    for k in range(mesh.K):
+        j = 0
+        while j + 1 < max_levels and (2.0 ** (j + 1)) * dtmin <= dt[k] * (1.0 + LEVEL_TIE_TOL):
+            j += 1
+        lev[k] = 1 + j
+    while True:
+        new = np.minimum(lev, lev[mesh.etoe].min(axis=1) + 1)
+        if np.array_equal(new, lev):
+            return lev, dtmin
+        lev = new
+
+
 def time_step(mesh: Mesh, N: int, cfl: float, a_max: float) -> float:
     """dt_min of Eq. 4.1: min over elements of CFL r_K / ((N+1)^2 a_max)."""
     return cfl * mesh.inradius.min() / ((N + 1) ** 2 * max(a_max, 1e-12))

@@ -50,7 +50,8 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from .mesh import Mesh, assign_levels, build_mesh, time_step, tvb_stencil, wave_speed
+from .mesh import (Mesh, assign_levels, build_mesh, element_wave_speeds, speed_levels, time_step,
+                   tvb_stencil, wave_speed)
 from .overint import gauss_exterior_map, overint_operators
 from .refelem import reference_element
 
@@ -78,6 +79,8 @@ class Params:
     thin_cut: float = 0.0      # > 0: momentum zeroed after the limiters where h < thin_cut
     max_levels: int = 1
     overint: bool = False      # weak form with cubature and Gauss rules (Section 3, Section 7)
+    regroup_every: int = 0     # multi-rate: regroup levels from the current wave speeds every
+                               # this many coarse steps (0: levels fixed from the mesh)
 
 
 @dataclass
@@ -137,6 +140,10 @@ class Solver:
     def __init__(self, vx, vy, etov, N: int, params: Optional[Params] = None,
                  ghost: Optional[Callable] = None, bc=None):
         self.p = params or Params()
+        if 0 < self.p.regroup_every < 3:
+            # a level change re-samples three history values per element; by the
+            # third coarse step after one they are all the element's own again
+            raise ValueError("regroup_every must be 0 or at least 3 coarse steps")
         self.N = N
         self.ref = reference_element(N)
         self.mesh: Mesh = build_mesh(vx, vy, etov, self.ref, bc)
@@ -175,6 +182,11 @@ class Solver:
                       np.asarray(hv, np.float64)]).copy()
         a_max = wave_speed(q[0], q[1], q[2], self.p.g, self.p.hvel)
         self.dt_min = time_step(self.mesh, self.N, self.p.cfl, a_max)
+        if self.p.regroup_every > 0:
+            # levels from the elements' own wave speeds, regrouped as the run goes
+            sp = element_wave_speeds(self.mesh, q[0], q[1], q[2], self.p.g, self.p.hvel)
+            self.levels, self.dt_min = speed_levels(self.mesh, self.N, self.p.cfl, sp, self.p.max_levels)
+        self.coarse_steps = 0
         if limit:
             q, self.flags = self.limit(q)
         self.q = q
@@ -565,7 +577,63 @@ class Solver:
             self.q = qt
             self.flags = flags
             self.t += self.dt_min
+        self.coarse_steps += 1
+        if self.p.regroup_every > 0 and self.coarse_steps % self.p.regroup_every == 0:
+            self.regroup()
         return self.q
+
+    def regroup(self):
+        """Regroup the elements into levels from the current wave speeds (the
+        option named after Algorithm 4.1), at a coarse-step boundary: every
+        element's allowable step from Eq. 4.1 with its own wave speed (its
+        nodes and its face neighbours'), then the level rule and the 2:1
+        rule.  Needs a full history on every level (after the start-up
+        steps); otherwise nothing changes."""
+        st = self._mr
+        L = self.p.max_levels
+        if st is None or any(len(st["hist"][l]) < 3 for l in range(1, L + 1) if np.any(self.levels == l)):
+            return
+        q = self.q
+        sp = element_wave_speeds(self.mesh, q[0], q[1], q[2], self.p.g, self.p.hvel)
+        new_lev, new_dtmin = speed_levels(self.mesh, self.N, self.p.cfl, sp, L)
+        self.set_levels(new_lev, new_dtmin)
+
+    def set_levels(self, new_lev, new_dtmin):
+        """Move the elements to new levels (and a new finest step) at a
+        coarse-step boundary, where all levels are at the same time t.  Each
+        element's Adams-Bashforth history R(t - dt), R(t - 2 dt), R(t - 3 dt) at
+        its old step dt is replaced by the values at t - dt', t - 2 dt',
+        t - 3 dt' of the quadratic through it, dt' the element's new step: the
+        interpolant of the same degree as the AB3 rule, so a level change keeps
+        the method third order in smooth flow (not conservative to roundoff:
+        neighbours re-sample their histories at different times)."""
+        st = self._mr
+        L = self.p.max_levels
+        old_lev = self.levels
+        old_dt = self.dt_min * 2.0 ** (old_lev - 1)
+        K, Np = self.K, self.ref.Np
+        S = np.zeros((3, 3, K, Np))   # sample s (t - (s+1) dt), field, element, node
+        for l in range(1, L + 1):
+            sel = old_lev == l
+            if not np.any(sel):
+                continue
+            for sidx in range(3):
+                S[sidx][:, sel, :] = st["hist"][l][sidx]
+        rho = (new_dtmin * 2.0 ** (np.asarray(new_lev) - 1)) / old_dt          # (K,)
+        new = np.zeros_like(S)
+        for sidx in range(3):
+            tau = -(sidx + 1) * rho[None, :, None]
+            l1 = (tau + 2.0) * (tau + 3.0) / 2.0
+            l2 = -(tau + 1.0) * (tau + 3.0)
+            l3 = (tau + 1.0) * (tau + 2.0) / 2.0
+            new[sidx] = l1 * S[0] + l2 * S[1] + l3 * S[2]
+        st["hist"] = [[] for _ in range(L + 1)]
+        for l in range(1, L + 1):
+            sel = new_lev == l
+            if np.any(sel):
+                st["hist"][l] = [new[sidx][:, sel, :] for sidx in range(3)]
+        self.levels = np.asarray(new_lev)
+        self.dt_min = new_dtmin
 
     def limit_multirate(self, q, active):
         p = self.p

@@ -25,7 +25,10 @@ seeded 2024 + instance number), with their final state, Jacobians, the
 instance's mass and time step and the sampled elements' final limiter codes.
 Runs the instances in a process pool (one BLAS thread each).
 
-    python tests/golden/make_golden.py c3 c4 c5
+c5_overint: the same ensemble and record with the over-integrated weak form
+(cubature and Gauss rules exact to degree 3N) instead of nodal collocation.
+
+    python tests/golden/make_golden.py c3 c4 c5 c5_overint
 """
 import os
 import sys
@@ -93,10 +96,10 @@ def make_sampled(name, wl, steps, n_samples=1024):
 
 
 def _c5_instance(args):
-    i, n_samples = args
+    i, n_samples, overint = args
     wl = W.c5()
     ins = wl.instances[i]
-    s = Solver(ins.vx, ins.vy, ins.etov, wl.N, Params(g=wl.g, cfl=wl.cfl))
+    s = Solver(ins.vx, ins.vy, ins.etov, wl.N, Params(g=wl.g, cfl=wl.cfl, overint=overint))
     x, y = s.nodes()
     s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry))
     m0 = s.mass()
@@ -111,15 +114,17 @@ def _c5_instance(args):
                 final_tvb=s.flags.tvb[idx], M=s.ref.M)
 
 
-def make_c5(n_samples=64, workers=4):
+def make_c5(n_samples=64, workers=4, overint=False):
     """Every instance of the ensemble through its own oracle; the records
-    are stacked along a leading instance axis."""
+    are stacked along a leading instance axis.  overint: the over-integrated
+    weak form (cubature and Gauss rules) instead of nodal collocation."""
     from concurrent.futures import ProcessPoolExecutor
     from threadpoolctl import threadpool_limits
     n_inst = len(W.c5().instances)
     with threadpool_limits(limits=1), ProcessPoolExecutor(max_workers=workers) as ex:
-        recs = list(ex.map(_c5_instance, [(i, n_samples) for i in range(n_inst)]))
-    out = os.path.join(HERE, "c5_oracle_samples.npz")
+        recs = list(ex.map(_c5_instance, [(i, n_samples, overint) for i in range(n_inst)]))
+    name = "c5_overint" if overint else "c5"
+    out = os.path.join(HERE, f"{name}_oracle_samples.npz")
     np.savez_compressed(out, elements=np.stack([r["elements"] for r in recs]),
                         h=np.stack([r["h"] for r in recs]), hu=np.stack([r["hu"] for r in recs]),
                         hv=np.stack([r["hv"] for r in recs]), J=np.stack([r["J"] for r in recs]),
@@ -128,7 +133,7 @@ def make_c5(n_samples=64, workers=4):
                         dt=np.array([r["dt"] for r in recs]),
                         final_pp=np.stack([r["final_pp"] for r in recs]),
                         final_tvb=np.stack([r["final_tvb"] for r in recs]),
-                        command="python tests/golden/make_golden.py c5")
+                        command=f"python tests/golden/make_golden.py {name}")
     print("wrote", out, flush=True)
 
 
@@ -145,5 +150,7 @@ if __name__ == "__main__":
             make_sampled("c4", W.c4(), 300)
         elif a == "c5":
             make_c5()
+        elif a == "c5_overint":
+            make_c5(overint=True)
         else:
             print(__doc__)

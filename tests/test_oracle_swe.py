@@ -477,3 +477,136 @@ def test_near_dry_front_stays_finite_at_order_4():
     tv = sum(fc[1] for fc in s.flag_counts)
     assert tv[3] > 0   # Eq. 5.3 at work
     assert abs(s.mass() - m0) / m0 < 1e-3
+
+
+# ------------------------------------------------------------- regrouping
+def test_regroup_history_remap_exact_for_quadratics():
+    """The re-sampling of a level change: a right-hand side that is a
+    quadratic in time is re-sampled exactly at the new step (coarser and
+    finer), and an unchanged level is an exact identity."""
+    wl = W.graded_beach(N=1)
+    ins = wl.instances[0]
+    s = Solver(ins.vx, ins.vy, ins.etov, 1, Params(max_levels=4, regroup_every=3, pp=False, tvb=False))
+    x, y = s.nodes()
+    s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry), limit=False)
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=(3, 3, s.K, s.ref.Np))
+    R = lambda t: c[0] + c[1] * t + c[2] * t * t   # noqa: E731
+    lev0 = s.levels.copy()
+    dt0 = s.dt_min * 2.0 ** (lev0 - 1)
+    hist = [[] for _ in range(5)]
+    for l in range(1, 5):
+        sel = lev0 == l
+        hist[l] = [R(-(i + 1) * dt0[None, :, None])[:, sel, :] for i in range(3)] if np.any(sel) else []
+    s._mr = {"hist": [list(h) for h in hist], "half": s.q.copy(), "tick": 0}
+    s.set_levels(lev0, s.dt_min)
+    for l in range(1, 5):
+        for a, b in zip(s._mr["hist"][l], hist[l]):
+            assert np.array_equal(a, b)
+    new = np.clip(lev0 + np.where(np.arange(s.K) % 2 == 0, 1, -1), 1, 4)
+    s.set_levels(new, 0.75 * s.dt_min)
+    dtn = s.dt_min * 2.0 ** (new - 1)
+    for l in range(1, 5):
+        sel = new == l
+        for i, a in enumerate(s._mr["hist"][l]):
+            want = R(-(i + 1) * dtn[None, :, None])[:, sel, :]
+            assert np.max(np.abs(a - want)) < 1e-12 * np.max(np.abs(want))
+
+
+def test_regroup_keeps_third_order():
+    """Two-level multi-rate AB3 from an exact history, with every element
+    moved to the other level every third coarse step (the shortest regroup
+    period: by then each level's three history samples are its own right-hand
+    sides again): the error against a fine RK4 reference still falls at
+    third order.  Each move re-samples the history with an O(dt^3) error, so a
+    linear re-sampling would leave O(dt^2) after the O(1/dt) moves."""
+    wl = W.c3(n0=2, n_bands=2)
+    ins = wl.instances[0]
+
+    def make_mr():
+        s = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=0.3, max_levels=2, pp=False, tvb=False))
+        x, y = s.nodes()
+        s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry), limit=False)
+        return s
+
+    s0 = make_mr()
+    dt0, B = s0.dt_min, s0.B
+    hq, T0, T, sub = dt0 / 4, 4 * dt0, 24 * dt0, 16
+
+    def rk4(q, h):
+        k1 = s0.rhs(q, B)
+        k2 = s0.rhs(q + 0.5 * h * k1, B)
+        k3 = s0.rhs(q + 0.5 * h * k2, B)
+        k4 = s0.rhs(q + h * k3, B)
+        return q + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+
+    q = s0.q.copy()
+    ref = []
+    n_total = int(round((T0 + T) / hq))
+    for i in range(n_total + 1):
+        ref.append(q.copy())
+        if i < n_total:
+            for _ in range(sub):
+                q = rk4(q, hq / sub)
+
+    def at(t):
+        return ref[int(round((t + T0) / hq))]
+
+    errs = []
+    for dt in (dt0, dt0 / 2, dt0 / 4):
+        s = make_mr()
+        s.dt_min = dt
+        s.q = at(0.0).copy()
+        hist = [[] for _ in range(3)]
+        for l in (1, 2):
+            dtl = dt * 2 ** (l - 1)
+            sel = s.levels == l
+            hist[l] = [s.rhs(at(-dtl), B)[:, sel, :], s.rhs(at(-2 * dtl), B)[:, sel, :],
+                       s.rhs(at(-3 * dtl), B)[:, sel, :]]
+        s._mr = {"hist": hist, "half": s.q.copy(), "tick": 0}
+        for c in range(int(round(T / (2 * dt)))):
+            s.run(1)
+            if c % 3 == 2:
+                # every element to the other level; the finest step stays dt
+                # (levels 1 and 2 swap, which the 2:1 rule allows for two levels)
+                s.set_levels(3 - s.levels, dt)
+        errs.append(np.max(np.abs(s.q - at(T))))
+    errs = np.array(errs)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios > 6.5), (errs, ratios)
+
+
+def test_regroup_follows_the_wave_speeds():
+    """On the graded wet/dry beach the regrouped levels move with the flow
+    (some element changes level within 8 coarse steps), the run stays
+    non-negative, and regrouping every step equals never regrouping while no
+    level changes (the re-sampling is then the identity)."""
+    wl = W.graded_beach(N=2)
+    ins = wl.instances[0]
+
+    def make(regroup):
+        s = Solver(ins.vx, ins.vy, ins.etov, 2, Params(g=wl.g, cfl=wl.cfl, max_levels=4, regroup_every=regroup))
+        x, y = s.nodes()
+        s.set_state(*ins.initial(x, y), s.interpolate(ins.bathymetry))
+        return s
+
+    a = make(3)
+    lev0 = a.levels.copy()
+    changed = False
+    m0 = a.mass()
+    for _ in range(12):
+        a.run(1)
+        changed |= not np.array_equal(a.levels, lev0)
+    assert changed
+    assert a.q[0].min() >= 0.0
+    assert abs(a.mass() - m0) < 1e-5 * m0
+    b, c = make(3), make(10 ** 6)
+    b.run(3)
+    c.run(3)
+    assert np.array_equal(b.q, c.q)
+    if np.array_equal(b.levels, c.levels):
+        b.run(1)
+        c.run(1)
+        assert np.array_equal(b.q, c.q)
+    with pytest.raises(ValueError):
+        make(2)
