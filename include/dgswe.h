@@ -123,6 +123,15 @@ typedef struct dg_params {
                             /* quadrature, both exact to degree 3N (Section 3 and the */
                             /* Volume/Surface kernels of Section 7): N <= 5, on the   */
                             /* vector-ALU paths DG_PLAIN_FP32 and DG_FUSED_FP32        */
+    int32_t regroup_every;  /* multi-rate only (max_levels >= 2): 0 = levels fixed    */
+                            /* from the mesh (Section 4); >= 3 = levels from every    */
+                            /* element's own wave speed (Eq. 4.1 per element, its     */
+                            /* nodes and face neighbours), at dg_prepare and again    */
+                            /* every regroup_every coarse steps (the option named     */
+                            /* after Algorithm 4.1).  At a regroup each element's AB  */
+                            /* history is re-sampled at its new step from the         */
+                            /* quadratic through it; graph replay is off.  1, 2 or    */
+                            /* < 0 is DG_EINVAL                                        */
 } dg_params;
 
 /* Fill *p with the defaults: g 9.81, cfl 0.5, h0 = eps = 1e-5, hvel 1e-3, M 10, nu 1.5,
@@ -215,7 +224,8 @@ int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double*
 int32_t dg_get_connectivity(const dg_solver* h, int32_t inst, int32_t* etoe, int8_t* etof);
 
 /* Multi-rate level (1 = finest) of every element of instance `inst`, and the
- * instance's dt_min (0 before its state is set). */
+ * instance's dt_min (0 before its state is set); with regrouping, the current
+ * levels and step (from dg_prepare on). */
 int32_t dg_get_levels(const dg_solver* h, int32_t inst, int8_t* level, double* dt_min);
 
 /* TVB stencil of instance `inst`: pair[K][3][2] face indices used for edge i,
@@ -257,20 +267,21 @@ int32_t dg_get_diagnostics_noalloc(dg_solver* h, int32_t inst, double* out_devic
 /* Checkpoint: the full time-stepping state (states, RHS history, half-step
  * traces, counters) as an opaque byte blob; dg_checkpoint_bytes gives the
  * size: a 256-byte header (solver shape, the multi-rate schedule state, the
- * step and finest-level tick counts), one 32-byte record per instance (the
+ * step and finest-level tick counts), one 48-byte record per instance (the
  * vertical datum its stored levels are relative to, its time step, its
- * initial wave-speed bound and a hash of its FP64 bathymetry), then the
+ * initial wave-speed bound, a hash of its FP64 bathymetry, and its time
+ * origin at the last regroup), every element's multi-rate level, then the
  * device state; any number of instances.  Restoring onto a solver created
  * with the same meshes, params and bathymetry continues bit-identically,
- * single-rate or multi-rate, whatever state dg_set_state staged on it: the
- * restore takes the datum and time step of every instance from the blob
- * (rebuilding the shifted bed on the device), so each instance's simulated
- * time is the tick count times the restored time step.  A later dg_prepare
- * returns to the staged state.  Both synchronise `stream`.  Errors:
- * DG_EINVAL for a buffer shorter than dg_checkpoint_bytes, a blob of another
- * solver shape (K, Np, levels, instances) or bathymetry, or a corrupt blob
- * (schedule state outside its ranges, negative counts, a non-finite or
- * non-positive instance record), each detected before anything is copied;
+ * single-rate, multi-rate or regrouping, whatever state dg_set_state staged on
+ * it: the restore takes the datum, time step and levels of every instance
+ * from the blob (rebuilding the shifted bed and, for regrouped levels, the
+ * element order on the device).  A later dg_prepare returns to the staged
+ * state.  Both synchronise `stream`.  Errors: DG_EINVAL for a buffer shorter
+ * than dg_checkpoint_bytes, a blob of another solver shape (K, Np, levels,
+ * instances) or bathymetry, or a corrupt blob (schedule state outside its
+ * ranges, negative counts, a non-finite or non-positive instance record, a
+ * level out of range), each detected before anything is copied;
  * dg_get_checkpoint DG_ENOTBOUND before any state is on the device;
  * dg_set_checkpoint DG_ESTATE before dg_prepare or dg_advance. */
 int32_t dg_checkpoint_bytes(const dg_solver* h, int64_t* bytes);

@@ -140,6 +140,8 @@ class Solver:
     def __init__(self, vx, vy, etov, N: int, params: Optional[Params] = None,
                  ghost: Optional[Callable] = None, bc=None):
         self.p = params or Params()
+        if self.p.regroup_every > 0 and self.p.max_levels < 2:
+            raise ValueError("regrouping is a multi-rate option (max_levels >= 2)")
         if 0 < self.p.regroup_every < 3:
             # a level change re-samples three history values per element; by the
             # third coarse step after one they are all the element's own again

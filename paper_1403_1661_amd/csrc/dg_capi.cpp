@@ -59,6 +59,10 @@ struct Inst {
     // (dg_prepare starts from them; a restored checkpoint brings its own)
     float staged_datum = 0.f;
     double staged_dt_min = 0.0, staged_a_max = 0.0;
+    std::vector<double> speed0;   // per-element wave speed of the staged state (regrouping)
+    // simulated time: t_base + (ticks - tick_base) dt_min (dt_min changes at regroups)
+    double t_base = 0.0;
+    int64_t tick_base = 0;
 };
 
 }  // namespace
@@ -85,6 +89,7 @@ struct dg_solver {
     int parity[kMaxLevels] = {0}, head[kMaxLevels] = {0}, nhist[kMaxLevels] = {0};
     long long steps = 0;     // coarse steps since dg_prepare
     int64_t ticks = 0;       // finest-level ticks since dg_prepare (simulated time = ticks * dt_min)
+    int64_t regroups = 0;    // regroupings since dg_prepare
     // execution
     hipStream_t exec = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -154,6 +159,128 @@ static int engine_of(int precision) {
         case DG_FUSED_BF16X6: return ENGINE_MFMA_BF16X6;
         default: return ENGINE_VALU;
     }
+}
+
+// Element order of the device arrays: by (level, instance, local index), so
+// that every level is one contiguous range.
+static void sort_elements(dg_solver* h) {
+    h->perm.resize(h->K);
+    h->inv.resize(h->K);
+    h->inst_of.resize(h->K);
+    int pos = 0;
+    h->lev_begin.assign(h->L, 0);
+    h->lev_end.assign(h->L, 0);
+    for (int l = 1; l <= h->L; ++l) {
+        h->lev_begin[l - 1] = pos;
+        for (size_t i = 0; i < h->inst.size(); ++i) {
+            const Inst& I = h->inst[i];
+            for (int k = 0; k < I.mesh.K; ++k) {
+                if (I.mesh.level[k] != l) continue;
+                const int gidx = I.offset + k;
+                h->perm[pos] = gidx;
+                h->inv[gidx] = pos;
+                h->inst_of[pos] = int(i);
+                ++pos;
+            }
+        }
+        h->lev_end[l - 1] = pos;
+    }
+}
+
+// Wave speed of every element for grouping: max |(u,v)| + sqrt(g h) over
+// its nodes and its face neighbours' nodes (desingularised velocity),
+// floored at 1e-12.  State in the instance's element order, [K][Np].
+static void element_speeds(const HostMesh& m, int Np, const double* hh, const double* hu, const double* hv,
+                           double g, double hvel, std::vector<double>& a) {
+    std::vector<double> node(m.K, 0.0);
+    for (int k = 0; k < m.K; ++k) {
+        double mx = 0.0;
+        for (int j = 0; j < Np; ++j) {
+            const size_t t = size_t(k) * Np + j;
+            const double d = hh[t];
+            const double f = 2.0 * d / (d * d + std::fmax(d * d, hvel * hvel));
+            mx = std::fmax(mx, std::hypot(hu[t] * f, hv[t] * f) + std::sqrt(g * std::fmax(d, 0.0)));
+        }
+        node[k] = mx;
+    }
+    a.assign(m.K, 0.0);
+    for (int k = 0; k < m.K; ++k) {
+        double mx = node[k];
+        for (int f = 0; f < 3; ++f) mx = std::fmax(mx, node[m.etoe[3 * k + f]]);
+        a[k] = std::fmax(mx, 1e-12);
+    }
+}
+
+// Levels from each element's own step dt_k = cfl r_k / ((N+1)^2 a_k) (Eq. 4.1
+// with a per element): 2^(l-1) dt_min <= dt_k < 2^l dt_min with a tie
+// tolerance of 1e-12, capped at L, then the 2:1 rule across faces.  Writes
+// m.level and returns dt_min.
+static double speed_levels(HostMesh& m, int N, double cfl, const std::vector<double>& a, int L) {
+    std::vector<double> dt(m.K);
+    double dtmin = 1e300;
+    for (int k = 0; k < m.K; ++k) {
+        dt[k] = cfl * m.inradius[k] / (double((N + 1) * (N + 1)) * a[k]);
+        dtmin = std::fmin(dtmin, dt[k]);
+    }
+    m.level.assign(m.K, 1);
+    for (int k = 0; k < m.K; ++k) {
+        int j = 0;
+        while (j + 1 < L && std::ldexp(dtmin, j + 1) <= dt[k] * (1.0 + 1e-12)) ++j;
+        m.level[k] = int8_t(1 + j);
+    }
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        std::vector<int8_t> nxt(m.level);
+        for (int k = 0; k < m.K; ++k)
+            for (int f = 0; f < 3; ++f) {
+                const int nb = m.etoe[3 * k + f];
+                if (m.level[nb] + 1 < nxt[k]) nxt[k] = int8_t(m.level[nb] + 1);
+            }
+        for (int k = 0; k < m.K; ++k)
+            if (nxt[k] != m.level[k]) changed = true;
+        m.level.swap(nxt);
+    }
+    return dtmin;
+}
+
+// After the instances' levels changed: new element order, and every host
+// staging array moved to it.  Returns, for every old sorted position, its
+// new one (for the caller's own arrays).
+template <typename T>
+static void move_rows(std::vector<T>& v, size_t row, size_t fields, const std::vector<int>& to) {
+    if (v.empty()) return;
+    const size_t K = to.size();
+    std::vector<T> out(v.size());
+    for (size_t c = 0; c < fields; ++c)
+        for (size_t o = 0; o < K; ++o)
+            std::copy(v.begin() + (c * K + o) * row, v.begin() + (c * K + o + 1) * row,
+                      out.begin() + (c * K + size_t(to[o])) * row);
+    v.swap(out);
+}
+
+static std::vector<int> resort(dg_solver* h) {
+    const std::vector<int> old_perm = h->perm;
+    sort_elements(h);
+    const int K = h->K;
+    std::vector<int> to(K);
+    for (int o = 0; o < K; ++o) to[o] = h->inv[old_perm[o]];
+    const size_t Np = size_t(h->Np);
+    move_rows(h->geo, 16, 1, to);
+    move_rows(h->stencil, 16, 1, to);
+    move_rows(h->conn, 4, 1, to);
+    for (int sidx = 0; sidx < K; ++sidx)
+        for (int f = 0; f < 3; ++f) {
+            int& c = h->conn[4 * size_t(sidx) + f];
+            if (c >= 0) c = to[c];
+        }
+    move_rows(h->B64, Np, 1, to);
+    move_rows(h->Bh, Np, 1, to);
+    move_rows(h->Bl, Np, 1, to);
+    move_rows(h->dBh, Np, 2, to);
+    move_rows(h->Qh, Np, 3, to);
+    move_rows(h->Ql, Np, 1, to);
+    return to;
 }
 
 static void compute_layout(dg_solver* h) {
@@ -250,6 +377,10 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
     if (p->precision >= DG_FUSED_MFMA32 && p->N > 5)
         return fail(DG_EINVAL, "the MFMA contraction supports N <= 5");
     if (p->overint != 0 && p->overint != 1) return fail(DG_EINVAL, "overint must be 0 or 1");
+    if (p->regroup_every < 0 || (p->regroup_every > 0 && p->regroup_every < 3))
+        return fail(DG_EINVAL, "regroup_every must be 0 or at least 3 coarse steps");
+    if (p->regroup_every > 0 && p->max_levels < 2)
+        return fail(DG_EINVAL, "regrouping needs max_levels >= 2");
     if (p->overint && (p->N > 5 || p->precision > DG_FUSED_FP32))
         return fail(DG_EINVAL, "over-integration runs for N <= 5 on DG_PLAIN_FP32 / DG_FUSED_FP32");
     if (p->elems_per_block != 0) {
@@ -298,29 +429,7 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
     }
     if (total > (1LL << 30)) return fail(DG_EINVAL, "too many elements");
     h->K = int(total);
-    // sort by (level, instance, local index)
-    h->perm.resize(h->K);
-    h->inv.resize(h->K);
-    h->inst_of.resize(h->K);
-    std::vector<int> lev_g(h->K);
-    for (int i = 0; i < n_inst; ++i)
-        for (int k = 0; k < h->inst[i].mesh.K; ++k) lev_g[h->inst[i].offset + k] = h->inst[i].mesh.level[k];
-    int pos = 0;
-    h->lev_begin.assign(h->L, 0);
-    h->lev_end.assign(h->L, 0);
-    for (int l = 1; l <= h->L; ++l) {
-        h->lev_begin[l - 1] = pos;
-        for (int i = 0; i < n_inst; ++i)
-            for (int k = 0; k < h->inst[i].mesh.K; ++k) {
-                const int gidx = h->inst[i].offset + k;
-                if (lev_g[gidx] != l) continue;
-                h->perm[pos] = gidx;
-                h->inv[gidx] = pos;
-                h->inst_of[pos] = i;
-                ++pos;
-            }
-        h->lev_end[l - 1] = pos;
-    }
+    sort_elements(h.get());
     // static per-element device records
     const int K = h->K;
     h->geo.assign(size_t(K) * 16, 0.f);
@@ -717,6 +826,7 @@ int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double*
     I.staged_datum = I.datum;
     I.staged_dt_min = I.dt_min;
     I.staged_a_max = I.a_max;
+    if (h->p.regroup_every > 0) element_speeds(I.mesh, Np, hh, hu, hv, h->p.g, h->p.hvel, I.speed0);
     I.has_state = true;
     h->prepared = false;
     return DG_OK;
@@ -950,6 +1060,115 @@ static DiagArgs diag_args(dg_solver* h, int inst) {
     return a;
 }
 
+// Regroup the elements into levels from the current state (the option the
+// paper names after Algorithm 4.1), at a coarse-step boundary where every
+// level is at the same time t, all with a full Adams-Bashforth history.
+// Each element's samples R(t - dt), R(t - 2 dt), R(t - 3 dt) at its old step
+// are replaced by the quadratic through them at t - dt', t - 2 dt', t - 3 dt'
+// (dt' its new step); the device arrays are rebuilt in the new element order
+// with every level's state in buffer 0 and its ring normalised to head 0.
+static int regroup_now(dg_solver* h, hipStream_t s) {
+    HIPCHECK(hipStreamSynchronize(s));
+    const int K = h->K, Np = h->Np;
+    const size_t KNp = size_t(K) * Np;
+    const Layout& l = h->lay;
+    // current state (each level's parity) and history samples, old order
+    std::vector<float> q(3 * KNp);
+    std::vector<int16_t> ql(KNp);
+    std::vector<float> S[3];
+    for (int t = 0; t < 3; ++t) S[t].assign(3 * KNp, 0.f);
+    for (int lv = 0; lv < h->L; ++lv) {
+        const size_t b0 = size_t(h->lev_begin[lv]) * Np, n = size_t(h->lev_end[lv] - h->lev_begin[lv]) * Np;
+        if (!n) continue;
+        const char* Q = h->ws + l.Q[h->parity[lv]];
+        for (int c = 0; c < 3; ++c)
+            HIPCHECK(hipMemcpy(q.data() + c * KNp + b0, Q + (c * KNp + b0) * 4, n * 4, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(ql.data() + b0, Q + 12 * KNp + b0 * 2, n * 2, hipMemcpyDeviceToHost));
+        // ring: R(t - dt) in (head + 2) % 3, R(t - 2 dt) in (head + 1) % 3, R(t - 3 dt) in head
+        const int slot[3] = {(h->head[lv] + 2) % 3, (h->head[lv] + 1) % 3, h->head[lv]};
+        for (int t = 0; t < 3; ++t)
+            for (int c = 0; c < 3; ++c)
+                HIPCHECK(hipMemcpy(S[t].data() + c * KNp + b0, h->ws + l.R[slot[t]] + (c * KNp + b0) * 4, n * 4,
+                                   hipMemcpyDeviceToHost));
+    }
+    std::vector<uint8_t> flags(K);
+    HIPCHECK(hipMemcpy(flags.data(), h->ws + l.flags, K, hipMemcpyDeviceToHost));
+    // new levels per instance from the state's wave speeds (FP64 of the stored pairs)
+    std::vector<double> old_dt(K);
+    for (int sidx = 0; sidx < K; ++sidx) {
+        const Inst& I = h->inst[h->inst_of[sidx]];
+        old_dt[sidx] = std::ldexp(I.dt_min, I.mesh.level[h->perm[sidx] - I.offset] - 1);
+    }
+    for (Inst& I : h->inst) {
+        std::vector<double> hh(size_t(I.mesh.K) * Np), hu(hh.size()), hv(hh.size());
+        for (int k = 0; k < I.mesh.K; ++k)
+            for (int j = 0; j < Np; ++j) {
+                const size_t src = size_t(h->inv[I.offset + k]) * Np + j, dst = size_t(k) * Np + j;
+                hh[dst] = (double(q[src]) - double(h->Bh[src])) +
+                          (double(lo_decode(q[src], ql[src])) - double(lo_decode(h->Bh[src], h->Bl[src])));
+                hu[dst] = q[KNp + src];
+                hv[dst] = q[2 * KNp + src];
+            }
+        std::vector<double> a;
+        element_speeds(I.mesh, Np, hh.data(), hu.data(), hv.data(), h->p.g, h->p.hvel, a);
+        I.t_base += double(h->ticks - I.tick_base) * I.dt_min;
+        I.tick_base = h->ticks;
+        I.dt_min = speed_levels(I.mesh, h->p.N, h->p.cfl, a, h->L);
+    }
+    // re-sample each element's history at its new step (old order)
+    for (int sidx = 0; sidx < K; ++sidx) {
+        const Inst& I = h->inst[h->inst_of[sidx]];
+        const double rho = std::ldexp(I.dt_min, I.mesh.level[h->perm[sidx] - I.offset] - 1) / old_dt[sidx];
+        if (rho == 1.0) continue;
+        double w[3][3];
+        for (int t = 0; t < 3; ++t) {
+            const double tau = -(t + 1) * rho;
+            w[t][0] = (tau + 2.0) * (tau + 3.0) / 2.0;
+            w[t][1] = -(tau + 1.0) * (tau + 3.0);
+            w[t][2] = (tau + 1.0) * (tau + 2.0) / 2.0;
+        }
+        for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < Np; ++j) {
+                const size_t idx = c * KNp + size_t(sidx) * Np + j;
+                const double s0 = S[0][idx], s1 = S[1][idx], s2 = S[2][idx];
+                for (int t = 0; t < 3; ++t) S[t][idx] = float(w[t][0] * s0 + w[t][1] * s1 + w[t][2] * s2);
+            }
+    }
+    // new order; state, samples and flags move with it
+    const std::vector<int> to = resort(h);
+    move_rows(q, Np, 3, to);
+    move_rows(ql, Np, 1, to);
+    for (int t = 0; t < 3; ++t) move_rows(S[t], Np, 3, to);
+    move_rows(flags, 1, 1, to);
+    for (int sidx = 0; sidx < K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
+    // every level: state in buffer 0, ring head 0 (slot 2: R(t - dt), slot 1:
+    // R(t - 2 dt), slot 0: R(t - 3 dt), overwritten by the next right-hand side)
+    for (int lv = 0; lv < kMaxLevels; ++lv) {
+        h->parity[lv] = 0;
+        h->head[lv] = 0;
+        h->nhist[lv] = 2;
+    }
+    HIPCHECK(hipMemcpy(h->ws + l.Q[0], q.data(), q.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.Q[0] + 12 * KNp, ql.data(), ql.size() * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.R[2], S[0].data(), S[0].size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.R[1], S[1].data(), S[1].size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.R[0], S[2].data(), S[2].size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.flags, flags.data(), flags.size(), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.conn, h->conn.data(), h->conn.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.stencil, h->stencil.data(), h->stencil.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.Blo, h->Bl.data(), h->Bl.size() * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->ws + l.dB, h->dBh.data(), h->dBh.size() * 4, hipMemcpyHostToDevice));
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+        h->have_graph = false;
+    }
+    ++h->regroups;
+    return DG_OK;
+}
+
 // Capture the next `period` coarse steps (the ring x ping-pong period) from
 // the current schedule state into h->graph without running them.
 static int capture_graph(dg_solver* h) {
@@ -1022,6 +1241,19 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout& l = h->lay;
+    // regrouping: the initial levels from the staged state's wave speeds
+    if (h->p.regroup_every > 0) {
+        for (Inst& I : h->inst) I.staged_dt_min = speed_levels(I.mesh, h->p.N, h->p.cfl, I.speed0, h->L);
+        resort(h);
+        HIPCHECK(hipMemcpyAsync(h->ws + l.conn, h->conn.data(), h->conn.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(h->ws + l.stencil, h->stencil.data(), h->stencil.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        if (h->graph) {
+            (void)hipGraphExecDestroy(h->graph);
+            h->graph = nullptr;
+            h->have_graph = false;
+        }
+    }
     // back to the staged state's datum and time step (a restored checkpoint
     // may have replaced them)
     for (Inst& I : h->inst) {
@@ -1029,6 +1261,8 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
         I.datum = I.staged_datum;
         I.dt_min = I.staged_dt_min;
         I.a_max = I.staged_a_max;
+        I.t_base = 0.0;
+        I.tick_base = 0;
     }
     for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
     HIPCHECK(hipMemcpyAsync(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice, s));
@@ -1046,6 +1280,7 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
                             hipMemcpyHostToDevice, s));
     h->steps = 0;
     h->ticks = 0;
+    h->regroups = 0;
     // Q0 = TVB(PP(Pi_H Q0)), first line of Algorithm 5.1
     const int rc = enqueue_tick(h, 0, s, true);
     if (rc) return rc;
@@ -1069,7 +1304,8 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int period = 6;   // ring (3) and ping-pong (2) state repeats every 6 steps
     while (n_steps > 0) {
-        const bool graph_ok = h->p.use_graph && !h->profiling && all_started(h) && n_steps >= period;
+        const bool graph_ok = h->p.use_graph && !h->profiling && all_started(h) && n_steps >= period &&
+                              h->p.regroup_every == 0;
         if (graph_ok) {
             int key[3 * kMaxLevels];
             state_key(h, key);
@@ -1104,6 +1340,10 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream) {
         const int rc = enqueue_coarse_step(h, s);
         if (rc) return rc;
         --n_steps;
+        if (h->p.regroup_every > 0 && h->steps % h->p.regroup_every == 0 && all_started(h)) {
+            const int rr = regroup_now(h, s);
+            if (rr) return rr;
+        }
     }
     return DG_OK;
 }
@@ -1259,7 +1499,7 @@ int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream)
     d->min_depth = out[1];
     // simulated time from the tick count: independent of how the ticks were
     // grouped into launches, graph replays or checkpointed runs
-    d->time = double(h->ticks) * h->inst[inst].dt_min;
+    d->time = h->inst[inst].t_base + double(h->ticks - h->inst[inst].tick_base) * h->inst[inst].dt_min;
     d->steps = h->steps;
     d->negative_means = (int64_t)cnt[0];
     for (int q = 0; q < 3; ++q) d->pp_counts[q] = (int64_t)out[2 + q];
@@ -1292,10 +1532,14 @@ static_assert(sizeof(CkptHeader) <= 256, "checkpoint header exceeds its slot");
 struct CkptInst {
     double datum, dt_min, a_max;
     uint64_t bed_hash;
+    double t_base;
+    int64_t tick_base;
 };
-static constexpr uint64_t kCkptMagic = 0x4447535702ull;
+static constexpr uint64_t kCkptMagic = 0x4447535703ull;
 
-static size_t ckpt_prefix_bytes(const dg_solver* h) { return 256 + align256(h->inst.size() * sizeof(CkptInst)); }
+// header, instance records, then every element's level (global order)
+static size_t ckpt_levels_offset(const dg_solver* h) { return 256 + align256(h->inst.size() * sizeof(CkptInst)); }
+static size_t ckpt_prefix_bytes(const dg_solver* h) { return ckpt_levels_offset(h) + align256(size_t(h->K)); }
 
 // FNV-1a over the instance's FP64 bed values in the caller's element order
 static uint64_t bed_hash(const dg_solver* h, int inst) {
@@ -1342,6 +1586,10 @@ int32_t dg_get_checkpoint(dg_solver* h, void* blob, int64_t bytes, void* stream)
         ci[i].dt_min = h->inst[i].dt_min;
         ci[i].a_max = h->inst[i].a_max;
         ci[i].bed_hash = bed_hash(h, int(i));
+        ci[i].t_base = h->inst[i].t_base;
+        ci[i].tick_base = h->inst[i].tick_base;
+        int8_t* lv = reinterpret_cast<int8_t*>(b + ckpt_levels_offset(h)) + h->inst[i].offset;
+        std::copy(h->inst[i].mesh.level.begin(), h->inst[i].mesh.level.end(), lv);
     }
     HIPCHECK(hipMemcpy(b + pb, h->ws + h->lay.dyn_begin, h->lay.dyn_end - h->lay.dyn_begin,
                        hipMemcpyDeviceToHost));
@@ -1373,19 +1621,45 @@ int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* s
             return fail(DG_EINVAL, "corrupt checkpoint: instance " + std::to_string(i) + " record");
         if (ci[i].bed_hash != bed_hash(h, int(i)))
             return fail(DG_EINVAL, "checkpoint was taken over another bathymetry (instance " + std::to_string(i) + ")");
+        if (ci[i].tick_base < 0 || ci[i].tick_base > hd.ticks || !std::isfinite(ci[i].t_base))
+            return fail(DG_EINVAL, "corrupt checkpoint: instance " + std::to_string(i) + " time record");
     }
+    const int8_t* blev = reinterpret_cast<const int8_t*>(b + ckpt_levels_offset(h));
+    bool same_levels = true;
+    for (size_t i = 0; i < ci.size(); ++i)
+        for (int k = 0; k < h->inst[i].mesh.K; ++k) {
+            const int8_t v = blev[h->inst[i].offset + k];
+            if (v < 1 || v > h->L) return fail(DG_EINVAL, "corrupt checkpoint: element level out of range");
+            if (v != h->inst[i].mesh.level[k]) same_levels = false;
+        }
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHECK(hipStreamSynchronize(s));
     // the stored levels are relative to the checkpoint's datum and advance
     // with its time step: rebuild the shifted bed and the time-step slot of
     // the geometry records from them
-    const int Np = h->Np;
     for (size_t i = 0; i < ci.size(); ++i) {
         Inst& I = h->inst[i];
         I.datum = float(ci[i].datum);
         I.dt_min = ci[i].dt_min;
         I.a_max = ci[i].a_max;
+        I.t_base = ci[i].t_base;
+        I.tick_base = ci[i].tick_base;
         shift_bed(h, I, double(I.datum));
+    }
+    // a regrouped run: the blob's element order is that of its levels
+    if (!same_levels) {
+        for (size_t i = 0; i < ci.size(); ++i)
+            std::copy(blev + h->inst[i].offset, blev + h->inst[i].offset + h->inst[i].mesh.K,
+                      h->inst[i].mesh.level.begin());
+        resort(h);
+        HIPCHECK(hipMemcpy(h->ws + h->lay.conn, h->conn.data(), h->conn.size() * 4, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(h->ws + h->lay.stencil, h->stencil.data(), h->stencil.size() * 4, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(h->ws + h->lay.dB, h->dBh.data(), h->dBh.size() * 4, hipMemcpyHostToDevice));
+        if (h->graph) {
+            (void)hipGraphExecDestroy(h->graph);
+            h->graph = nullptr;
+            h->have_graph = false;
+        }
     }
     for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
     HIPCHECK(hipMemcpy(h->ws + h->lay.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice));

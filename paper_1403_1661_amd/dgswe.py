@@ -52,7 +52,8 @@ class Params(C.Structure):
                 ("eps", C.c_double), ("hvel", C.c_double), ("tvb_M", C.c_double), ("tvb_nu", C.c_double),
                 ("limiter_mask", C.c_int32), ("max_levels", C.c_int32),
                 ("precision", C.c_int32), ("dry_literal", C.c_int32), ("use_graph", C.c_int32),
-                ("elems_per_block", C.c_int32), ("thin_cut", C.c_double), ("overint", C.c_int32)]
+                ("elems_per_block", C.c_int32), ("thin_cut", C.c_double), ("overint", C.c_int32),
+                ("regroup_every", C.c_int32)]
 
 
 class Diag(C.Structure):
