@@ -380,7 +380,7 @@ def main():
     # volume term, Gauss surface term; N <= 5) on the vector-ALU kernels
     overint = None
     if not args.no_plain and wl.N <= 5:
-        e = make_solver(wl, "fused_fp32", use_graph=use_graph, tune=False, overint=1)
+        e = make_solver(wl, "fused_mfma32", use_graph=use_graph, tune=False, overint=1)
         warm_and_capture(e, warmup, use_graph, torch)
         te = timed(e, steps, torch)
         e.set_profiling(True)
@@ -391,7 +391,8 @@ def main():
         overint = {"value": per_step * steps / te, "ms_per_step": 1e3 * te / steps,
                    "rhs_kernel_avg_us": rhs_us,
                    "note": "weak form with cubature and Gauss rules exact to degree 3N; RHS kernel "
-                           "then the vector-ALU update and limiters"}
+                           "with its contractions on the matrix cores, then the vector-ALU update and "
+                           "limiters"}
         if not args.no_accuracy:
             overint["rel_l2_vs_oracle"] = accuracy_at_configured_steps(e, wl, f"{name}_overint")
         progress(f"over-integrated: {overint['ms_per_step']:.4f} ms/step, RHS kernel {rhs_us:.1f} us")

@@ -40,7 +40,7 @@ struct Layout {
     size_t dyn_begin, dyn_end;
     size_t B, Blo, dB, geo, conn, stencil;
     size_t Dr, Ds, LIFT, Amfma, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
-    size_t oIc, oPr, oPs, oP, oLg, oI1;
+    size_t oIc, oPr, oPs, oP, oLg, oI1, oT1, oT3;
     size_t diag_partial, diag_out;
     size_t total;
 };
@@ -330,6 +330,13 @@ static void compute_layout(dg_solver* h) {
         l.oP = take(nc * Np * 4);
         l.oLg = take(size_t(Np) * 3 * ng * 4);
         l.oI1 = take(ng * size_t(h->Nfp) * 4);
+        const int N = h->p.N;
+        if (N <= 5) {
+            l.oT1 = take(size_t(overint_mfma_t1(N)) * overint_mfma_s1(N) * 64 * 4);
+            l.oT3 = take(size_t(overint_mfma_tn(N)) * overint_mfma_t3_steps(N) * 64 * 4);
+        } else {
+            l.oT1 = l.oT3 = take(0);
+        }
     }
     l.diag_partial = take(256 * 16 * 8);
     l.diag_out = take(16 * 8);
@@ -381,8 +388,8 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         return fail(DG_EINVAL, "regroup_every must be 0 or at least 3 coarse steps");
     if (p->regroup_every > 0 && p->max_levels < 2)
         return fail(DG_EINVAL, "regrouping needs max_levels >= 2");
-    if (p->overint && (p->N > 5 || p->precision > DG_FUSED_FP32))
-        return fail(DG_EINVAL, "over-integration runs for N <= 5 on DG_PLAIN_FP32 / DG_FUSED_FP32");
+    if (p->overint && (p->N > 5 || p->precision > DG_FUSED_MFMA32))
+        return fail(DG_EINVAL, "over-integration runs for N <= 5 on DG_PLAIN_FP32, DG_FUSED_FP32 or DG_FUSED_MFMA32");
     if (p->elems_per_block != 0) {
         const bool mfma = p->precision >= DG_FUSED_MFMA32;
         const int valu_e = 256 / ((p->N + 1) * (p->N + 2) / 2);
@@ -712,6 +719,38 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
         HIPCHECK(up(l.oP, pp.data(), pp.size() * 4));
         HIPCHECK(up(l.oLg, lg.data(), lg.size() * 4));
         HIPCHECK(up(l.oI1, i1.data(), i1.size() * 4));
+        // matrix-core tables (B operands of v_mfma_f32_16x16x4f32 in lane order)
+        const int N = h->p.N;
+        if (N <= 5) {
+            const int T1 = overint_mfma_t1(N), S1 = overint_mfma_s1(N), TN = overint_mfma_tn(N);
+            const int SC = overint_mfma_sc(N), SG = overint_mfma_sg(N), ST3 = overint_mfma_t3_steps(N);
+            const int NC = oi.Ncub, NGF = 3 * oi.NG;
+            std::vector<float> t1(size_t(T1) * S1 * 64, 0.f), t3(size_t(TN) * ST3 * 64, 0.f);
+            for (int t = 0; t < T1; ++t)
+                for (int st = 0; st < S1; ++st)
+                    for (int ln = 0; ln < 64; ++ln) {
+                        const int cub = 16 * t + ln % 16, node = 4 * st + ln / 16;
+                        if (cub < NC && node < Np) t1[(size_t(t) * S1 + st) * 64 + ln] = float(oi.Ic(cub, node));
+                    }
+            for (int tn = 0; tn < TN; ++tn)
+                for (int st = 0; st < ST3; ++st)
+                    for (int ln = 0; ln < 64; ++ln) {
+                        const int node = 16 * tn + ln % 16;
+                        if (node >= Np) continue;
+                        double v = 0.0;
+                        if (st < 3 * SC) {
+                            const int ch = st / SC, kk = 4 * (st - ch * SC) + ln / 16;
+                            if (kk < NC) v = (ch == 0 ? oi.Pr : (ch == 1 ? oi.Ps : oi.P))(node, kk);
+                        } else {
+                            const int kk = 4 * (st - 3 * SC) + ln / 16;
+                            if (kk < NGF) v = -oi.Lg(node, kk);
+                        }
+                        (void)SG;
+                        t3[(size_t(tn) * ST3 + st) * 64 + ln] = float(v);
+                    }
+            HIPCHECK(up(l.oT1, t1.data(), t1.size() * 4));
+            HIPCHECK(up(l.oT3, t3.data(), t3.size() * 4));
+        }
     }
     HIPCHECK(up(l.conn, h->conn.data(), h->conn.size() * 4));
     HIPCHECK(up(l.stencil, h->stencil.data(), h->stencil.size() * 4));
@@ -875,6 +914,8 @@ static StepArgs base_step_args(dg_solver* h) {
     a.ops.oP = reinterpret_cast<const float*>(h->ws + l.oP);
     a.ops.oLg = reinterpret_cast<const float*>(h->ws + l.oLg);
     a.ops.oI1 = reinterpret_cast<const float*>(h->ws + l.oI1);
+    a.ops.oT1 = reinterpret_cast<const float*>(h->ws + l.oT1);
+    a.ops.oT3 = reinterpret_cast<const float*>(h->ws + l.oT3);
     a.g = float(h->p.g);
     a.h0 = float(h->p.h0);
     a.eps = float(h->p.eps);

@@ -945,6 +945,277 @@ struct BufF32 {
     }
 };
 
+
+// ---------------------------------------------------------------------------
+// The same right-hand side with its contractions on the matrix cores
+// (v_mfma_f32_16x16x4f32).  One wave = 4 elements, lane 16 e + c; blocks of
+// one wave, so waves never wait on each other.
+//  * stage 1: [h, d, hu, hv] and [dB/dx, dB/dy] at the cubature nodes as
+//    X1^T Ic^T, rows (element, field) and columns the cubature nodes, so lane
+//    16 e + c receives element e's values at cubature node 16 t + c of
+//    column tile t;
+//  * stage 2: that lane forms cF1, cF2 and cS there (perturbation form as in
+//    the vector kernel);
+//  * faces: exterior traces at the face nodes and the numerical flux at the
+//    Gauss points, lanes looping over the element's points;
+//  * stage 3: R^T = X3^T [Pr Ps P -L^g]^T, rows (element, field) and columns
+//    the nodes, the K range cF1 | cF2 | cS | Fscale Fn* passed through one
+//    LDS buffer in four chunks; lane 16 e + c receives R of element e at node
+//    16 tn + c.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
+    constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, nF = 3 * (N + 1);
+    constexpr int Q = overint_points(N), NC = Q * Q, NG = Q, NGF = 3 * Q;
+    constexpr int S1 = overint_mfma_s1(N), T1 = overint_mfma_t1(N), SC = overint_mfma_sc(N);
+    constexpr int SG = overint_mfma_sg(N), TN = overint_mfma_tn(N), ST3 = overint_mfma_t3_steps(N);
+    constexpr int KC = 4 * SC, KG = 4 * SG;
+    constexpr int X1S = 4 * S1 + 4;                     // row strides padded off the bank period
+    constexpr int XS = (KC > KG ? KC : KG) + 4;
+    constexpr int NI = (NGF + 15) / 16;                 // Gauss points per lane
+    __shared__ __attribute__((aligned(16))) float sX1[2][16][X1S];
+    __shared__ __attribute__((aligned(16))) float sX3[16][XS];
+    __shared__ float sNd[4][4][Np];                     // own h, d, hu, hv at the nodes
+    __shared__ float sFn[4][5][nF];                     // exterior h, hu, hv, d; B+ - B-, own face nodes
+    __shared__ float sFg[4][3][NGF];                    // Fscale Fn* at the Gauss points
+    __shared__ float sLam[4][NGF];
+
+    const int lane = threadIdx.x;
+    const int e = lane >> 4, c = lane & 15;
+    const int k = a.k_begin + xcd_remap(blockIdx.x, gridDim.x) * 4 + e;
+    const bool live = k < a.k_end;
+    const int kc = live ? k : a.k_end - 1;            // clamped: loads stay in range
+    const long long KNp = a.KNp;
+    const float g = a.g, hvel = a.hvel;
+    const LevelArgs L = pick_level(a, level_of(a, kc));
+    const float* Qs = a.Q[L.parity];
+    const short* Qlo = reinterpret_cast<const short*>(Qs + 3 * KNp);
+    const long long b0 = (long long)kc * Np;
+    const float etak = Qs[b0];
+    const float lok = lo_decode(etak, Qlo[b0]);
+    // ---- nodal data into the stage-1 rows and the node table
+    for (int j = c; j < 4 * S1; j += 16) {
+        float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (j < Np) {
+            const long long idx = b0 + j;
+            const float eta = Qs[idx];
+            const float lo = lo_decode(eta, Qlo[idx]);
+            const float Bn = a.B[idx];
+            const float bl = lo_decode(Bn, a.Blo[idx]);
+            v[0] = (eta - Bn) + (lo - bl);
+            v[1] = (eta - etak) + (lo - lok);
+            v[2] = Qs[KNp + idx];
+            v[3] = Qs[2 * KNp + idx];
+            v[4] = a.dB[idx];
+            v[5] = a.dB[KNp + idx];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) sNd[e][f][j] = v[f];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sX1[0][4 * e + f][j] = v[f];
+        sX1[1][4 * e + 0][j] = v[4];
+        sX1[1][4 * e + 1][j] = v[5];
+        sX1[1][4 * e + 2][j] = 0.f;
+        sX1[1][4 * e + 3][j] = 0.f;
+    }
+    wave_lds_sync();
+    // ---- stage 1 on the matrix cores
+    const int ar = lane & 15, ak = lane >> 4;
+    floatx4 acc1[2][T1];
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int t = 0; t < T1; ++t) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < S1; ++st)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sX1[tr][ar][4 * st + ak],
+                                                           ldg(a.ops.oT1, (unsigned)((t * S1 + st) * 64 + lane)),
+                                                           acc, 0, 0, 0);
+            acc1[tr][t] = acc;
+        }
+    // ---- stage 2: fluxes and source at this lane's cubature nodes
+    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * (unsigned)kc);   // rx, ry, sx, sy
+    float cf[T1][8];
+#pragma unroll
+    for (int t = 0; t < T1; ++t) {
+        const bool on = 16 * t + c < NC;
+        const float h = acc1[0][t][0], d = acc1[0][t][1], hu = acc1[0][t][2], hv = acc1[0][t][3];
+        const float bx = acc1[1][t][0], by = acc1[1][t][1];
+        const float fv = vel_factor(h, hvel);
+        const float u = hu * fv, v = hv * fv;
+        const float pr = 0.5f * g * (d * (2.f * h - d));
+        const float F[3] = {hu, hu * u + pr, hu * v};
+        const float G[3] = {hv, hv * u, hv * v + pr};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            cf[t][r] = on ? g0.x * F[r] + g0.y * G[r] : 0.f;
+            cf[t][3 + r] = on ? g0.z * F[r] + g0.w * G[r] : 0.f;
+        }
+        cf[t][6] = on ? -g * d * bx : 0.f;
+        cf[t][7] = on ? -g * d * by : 0.f;
+    }
+    // ---- faces: exterior traces at the own face nodes
+    const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
+    const float* gk = a.geo + 16LL * kc;
+    for (int pn = c; pn < nF; pn += 16) {
+        const int f = pn / Nfp, j = pn - f * Nfp;
+        const int n = face_node_index(N, pn);
+        const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
+        float hP, huP, hvP, dP, dB;
+        if (nb >= 0) {
+            const int f2 = (cn.w >> (2 * f)) & 3;
+            const LevelArgs L2 = pick_level(a, level_of(a, nb));
+            const long long id2 = (long long)nb * Np + face_node_index(N, f2 * Nfp + (Nfp - 1 - j));
+            const float BP = a.B[id2];
+            const float blP = lo_decode(BP, a.Blo[id2]);
+            const long long idM = b0 + n;
+            const float BM = a.B[idM];
+            const float blM = lo_decode(BM, a.Blo[idM]);
+            float etaP, loP = 0.f;
+            if (L2.active || a.half == nullptr) {
+                const float* Q2 = a.Q[L2.parity];
+                etaP = Q2[id2];
+                huP = Q2[KNp + id2];
+                hvP = Q2[2 * KNp + id2];
+                loP = lo_decode(etaP, reinterpret_cast<const short*>(Q2 + 3 * KNp)[id2]);
+            } else {
+                const long long hid = (long long)nb * nF + f2 * Nfp + (Nfp - 1 - j);
+                etaP = a.half[hid];
+                huP = a.half[a.KnF + hid];
+                hvP = a.half[2 * a.KnF + hid];
+            }
+            hP = (etaP - BP) + (loP - blP);
+            dP = (etaP - etak) + (loP - lok);
+            dB = (BP - BM) + (blP - blM);
+        } else {   // reflective wall: the mirror state, same bed
+            const float nx = gk[4 + f], ny = gk[7 + f];
+            const float huM = sNd[e][2][n], hvM = sNd[e][3][n];
+            const float mn = huM * nx + hvM * ny;
+            hP = sNd[e][0][n];
+            huP = huM - 2.f * mn * nx;
+            hvP = hvM - 2.f * mn * ny;
+            dP = sNd[e][1][n];
+            dB = 0.f;
+        }
+        sFn[e][0][pn] = hP;
+        sFn[e][1][pn] = huP;
+        sFn[e][2][pn] = hvP;
+        sFn[e][3][pn] = dP;
+        sFn[e][4][pn] = dB;
+    }
+    wave_lds_sync();
+    // ---- numerical flux at the Gauss points (lanes loop over the element's points)
+    float gh[NI][8];   // hsM, hsP, uM, vM, uP, vP, jump, pressure part (without the jump term)
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int pg = c + 16 * it;
+        for (int q = 0; q < 8; ++q) gh[it][q] = 0.f;
+        if (pg >= NGF) continue;
+        const int f = pg / NG, gq = pg - f * NG;
+        float hM = 0.f, dM = 0.f, huM = 0.f, hvM = 0.f, hP = 0.f, huP = 0.f, hvP = 0.f, dP = 0.f, dB = 0.f;
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j) {
+            const float w = ldg(a.ops.oI1, (unsigned)(gq * Nfp + j));
+            const int n = face_node_index(N, f * Nfp + j);
+            const int t = f * Nfp + j;
+            hM += w * sNd[e][0][n];
+            dM += w * sNd[e][1][n];
+            huM += w * sNd[e][2][n];
+            hvM += w * sNd[e][3][n];
+            hP += w * sFn[e][0][t];
+            huP += w * sFn[e][1][t];
+            hvP += w * sFn[e][2][t];
+            dP += w * sFn[e][3][t];
+            dB += w * sFn[e][4][t];
+        }
+        const float nx = gk[4 + f], ny = gk[7 + f];
+        const float hsM = fmaxf(0.f, hM - fmaxf(0.f, dB));
+        const float hsP = fmaxf(0.f, hP - fmaxf(0.f, -dB));
+        const float jump = (hsM > 0.f && hsP > 0.f) ? dP - dM : hsP - hsM;
+        const float fM = vel_factor(hM, hvel), fP = vel_factor(hP, hvel);
+        const float uM = huM * fM, vM = hvM * fM, uP = huP * fP, vP = hvP * fP;
+        const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
+        sLam[e][pg] = fmaxf(fabsf(unM) + sqrtf(g * hsM), fabsf(unP) + sqrtf(g * hsP));
+        gh[it][0] = hsM;
+        gh[it][1] = hsP;
+        gh[it][2] = uM;
+        gh[it][3] = vM;
+        gh[it][4] = uP;
+        gh[it][5] = vP;
+        gh[it][6] = jump;
+        gh[it][7] = 0.5f * g * (dM * (2.f * hM - dM));
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int pg = c + 16 * it;
+        if (pg >= NGF) continue;
+        const int f = pg / NG;
+        float lam = sLam[e][f * NG];
+#pragma unroll
+        for (int t = 1; t < NG; ++t) lam = fmaxf(lam, sLam[e][f * NG + t]);
+        const float nx = gk[4 + f], ny = gk[7 + f], fs = gk[10 + f];
+        const float hsM = gh[it][0], hsP = gh[it][1], uM = gh[it][2], vM = gh[it][3];
+        const float uP = gh[it][4], vP = gh[it][5], jump = gh[it][6];
+        const float unM = uM * nx + vM * ny, unP = uP * nx + vP * ny;
+        const float pc = gh[it][7] + 0.25f * g * jump * (hsP + hsM);
+        sFg[e][0][pg] = fs * (0.5f * (hsM * unM + hsP * unP) - 0.5f * lam * jump);
+        sFg[e][1][pg] = fs * (0.5f * (hsM * uM * unM + hsP * uP * unP) + pc * nx - 0.5f * lam * (hsP * uP - hsM * uM));
+        sFg[e][2][pg] = fs * (0.5f * (hsM * vM * unM + hsP * vP * unP) + pc * ny - 0.5f * lam * (hsP * vP - hsM * vM));
+    }
+    // ---- stage 3: four K chunks through the LDS buffer
+    floatx4 acc3[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) acc3[tn] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        wave_lds_sync();   // the previous chunk's reads (and the flux writes) are done
+        if (ch < 3) {
+            // rows (e, r): cF1_r, cF2_r or cS_r (cS_h = 0) at cubature node 16 t + c
+#pragma unroll
+            for (int t = 0; t < T1; ++t) {
+                const int cp = 16 * t + c;
+                if (cp < KC) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+                        sX3[4 * e + r][cp] = ch == 0 ? cf[t][r] : (ch == 1 ? cf[t][3 + r] : (r == 0 ? 0.f : cf[t][5 + r]));
+                    sX3[4 * e + 3][cp] = 0.f;
+                }
+            }
+        } else {
+            for (int pg = c; pg < KG; pg += 16) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) sX3[4 * e + r][pg] = pg < NGF ? sFg[e][r][pg] : 0.f;
+                sX3[4 * e + 3][pg] = 0.f;
+            }
+        }
+        wave_lds_sync();
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int nst = ch < 3 ? SC : SG;
+        const int off = ch < 3 ? ch * SC : 3 * SC;
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+            for (int st = 0; st < nst; ++st)
+                acc3[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    sX3[ar][4 * st + ak], ldg(a.ops.oT3, (unsigned)(((tn * ST3) + off + st) * 64 + lane)), acc3[tn],
+                    0, 0, 0);
+    }
+    // ---- lane 16 e + c holds R of element e at node 16 tn + c (rows 4 e .. 4 e + 2)
+    if (!live) return;
+    float* R0 = a.R[L.slot[0]];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        const int node = 16 * tn + c;
+        if (node >= Np) continue;
+        const long long idx = (long long)k * Np + node;
+        R0[idx] = acc3[tn][0];
+        R0[KNp + idx] = acc3[tn][1];
+        R0[2 * KNp + idx] = acc3[tn][2];
+    }
+}
+
 // occupancy target (waves per SIMD) of the matrix-core kernel: what its
 // register use allows without spills (the BF16 splits and the multi-rate
 // bookkeeping hold more live values; N = 5 holds two accumulator tiles)
@@ -1776,6 +2047,10 @@ template <int N>
 static int launch_rhs_overint_n(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
+    if (a.engine == ENGINE_MFMA_F32) {
+        dispatch(rhs_overint_mfma_kernel<N>, (n + 3) / 4, 64, s, a, e0, e1);
+        return check_launch("over-integrated rhs kernel (matrix cores)");
+    }
     constexpr int E = OShape<N>::E;
     dispatch(rhs_overint_kernel<N>, (n + E - 1) / E, 256, s, a, e0, e1);
     return check_launch("over-integrated rhs kernel");

@@ -69,11 +69,24 @@ struct DevOps {
     const float* oP;
     const float* oLg;
     const float* oI1;
+    // matrix-core tables of the over-integrated form, B operands of
+    // v_mfma_f32_16x16x4f32 in lane order (see overint_mfma_* below)
+    const float* oT1;      // Ic^T: [tile t][step st][lane l] = Ic[16 t + l % 16][4 st + l / 16]
+    const float* oT3;      // [node tile][chunk][step][lane] = Op_chunk[node 16 tn + l % 16][4 st + l / 16],
+                           // chunks Pr, Ps, P (K = Ncub), -L^g (K = 3 NG)
 };
 
 // points per direction of the over-integrated rules (exact to degree 3N):
 // Ncub = q^2 cubature nodes, q Gauss points per face
 constexpr int overint_points(int N) { return (3 * N + 2) / 2; }
+// matrix-core form: steps of K = 4 over the nodes (stage 1), the cubature
+// nodes and the Gauss points (stage 3), and the column tiles of 16
+constexpr int overint_mfma_s1(int N) { return ((N + 1) * (N + 2) / 2 + 3) / 4; }
+constexpr int overint_mfma_t1(int N) { return (overint_points(N) * overint_points(N) + 15) / 16; }
+constexpr int overint_mfma_sc(int N) { return (overint_points(N) * overint_points(N) + 3) / 4; }
+constexpr int overint_mfma_sg(int N) { return (3 * overint_points(N) + 3) / 4; }
+constexpr int overint_mfma_tn(int N) { return ((N + 1) * (N + 2) / 2 + 15) / 16; }
+constexpr int overint_mfma_t3_steps(int N) { return 3 * overint_mfma_sc(N) + overint_mfma_sg(N); }
 
 struct StepArgs {
     int N, mode, engine;

@@ -3,7 +3,9 @@ cubature and Gauss rules; Section 7, Volume and Surface kernels) against the
 FP64 oracle run with the same rules (parameter overint): the right-hand
 side R = Pr cF1 + Ps cF2 + P cS - L^g Fn* on the vector-ALU kernel, followed
 by the same update and limiters as the nodal path.  Tolerance: relative L2
-of depth and momentum <= 1e-5; limiter flips counted and bounded."""
+of depth and momentum <= 1e-5; limiter flips counted and bounded.  The
+right-hand side runs on the vector ALU (plain_fp32, fused_fp32) or with its
+contractions on the matrix cores (fused_mfma32)."""
 import numpy as np
 import pytest
 
@@ -13,7 +15,9 @@ from helpers import flag_flips, gpu_solver, log, oracle_solver, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-PATHS = ["plain_fp32", "fused_fp32"]
+PATHS = ["plain_fp32", "fused_fp32", "fused_mfma32"]
+# vector-ALU and matrix-core right-hand-side kernels
+ENGINES = ["fused_fp32", "fused_mfma32"]
 
 
 def _require_gpu():
@@ -66,40 +70,45 @@ def test_overint_c1_trajectory(path):
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
-def test_overint_wetdry_orders(N):
-    g, o = _compare(f"wetdry-N{N}", W.small_wetdry(n=12, N=N), 60)
+@pytest.mark.parametrize("path", ENGINES)
+def test_overint_wetdry_orders(path, N):
+    g, o = _compare(f"wetdry-N{N}-{path}", W.small_wetdry(n=12, N=N), 60, path=path)
     assert g.diagnostics(0)["min_depth"] >= 0.0
 
 
 @pytest.mark.parametrize("case", ["dam", "ledge"])
 @pytest.mark.parametrize("N", [1, 3, 5])
-def test_overint_stepped_bed(case, N):
+@pytest.mark.parametrize("path", ENGINES)
+def test_overint_stepped_bed(path, case, N):
     wl = W.stepped_bed(case, N=N)
-    g, o = _compare(f"stepped-{case}-N{N}", wl, wl.steps)
+    g, o = _compare(f"stepped-{case}-N{N}-{path}", wl, wl.steps, path=path)
     assert g.diagnostics(0)["min_depth"] >= 0.0
 
 
 @pytest.mark.parametrize("N", [1, 3])
-def test_overint_multirate_wetdry(N):
+@pytest.mark.parametrize("path", ENGINES)
+def test_overint_multirate_wetdry(path, N):
     """Multi-rate AB3 (the graded beach, four levels): coarser inactive
     neighbours supply their half-step face traces, interpolated to the Gauss
     points like the current traces."""
-    g, o = _compare(f"mrab-N{N}", W.graded_beach(N=N), 10)
+    g, o = _compare(f"mrab-N{N}-{path}", W.graded_beach(N=N), 10, path=path)
     lev, _ = g.levels(0)
     assert np.array_equal(lev.astype(int), o.levels)
 
 
-def test_overint_reduced_c4():
+@pytest.mark.parametrize("path", ENGINES)
+def test_overint_reduced_c4(path):
     """The N = 5 precision workload (16 Fourier modes, fully wet) on a
     128x64x2 mesh, 30 steps."""
-    _compare("c4-reduced", W.c4(nx=128, ny=64), 30)
+    _compare(f"c4-reduced-{path}", W.c4(nx=128, ny=64), 30, path=path)
 
 
-def test_overint_ensemble():
+@pytest.mark.parametrize("path", ENGINES)
+def test_overint_ensemble(path):
     _require_gpu()
     wl = W.c5(n_inst=3, kmin=400, kmax=3000)
-    log("[oi-ensemble]")
-    g = gpu_solver(wl, precision="fused_fp32", overint=1)
+    log(f"[oi-ensemble] {path}")
+    g = gpu_solver(wl, precision=path, overint=1)
     g.advance(40)
     for i in range(3):
         o = oracle_solver(wl, inst=i, overint=True)
