@@ -161,12 +161,52 @@ static int engine_of(int precision) {
     }
 }
 
-// Element order of the device arrays: by (level, instance, local index), so
-// that every level is one contiguous range.
+// Morton (Z-order) key of every element's centroid, 16 bits per axis over
+// the instance's bounding box: elements close on the mesh get close keys.
+static std::vector<uint32_t> morton_keys(const HostMesh& m) {
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (int v = 0; v < m.Nv; ++v) {
+        x0 = std::fmin(x0, m.vx[v]);
+        x1 = std::fmax(x1, m.vx[v]);
+        y0 = std::fmin(y0, m.vy[v]);
+        y1 = std::fmax(y1, m.vy[v]);
+    }
+    const double sx = 65535.0 / std::fmax(x1 - x0, 1e-300), sy = 65535.0 / std::fmax(y1 - y0, 1e-300);
+    auto spread = [](uint32_t v) {
+        v &= 0xFFFFu;
+        v = (v | (v << 8)) & 0x00FF00FFu;
+        v = (v | (v << 4)) & 0x0F0F0F0Fu;
+        v = (v | (v << 2)) & 0x33333333u;
+        v = (v | (v << 1)) & 0x55555555u;
+        return v;
+    };
+    std::vector<uint32_t> key(m.K);
+    for (int k = 0; k < m.K; ++k) {
+        const int* t = &m.etov[3 * size_t(k)];
+        const double cx = (m.vx[t[0]] + m.vx[t[1]] + m.vx[t[2]]) / 3.0;
+        const double cy = (m.vy[t[0]] + m.vy[t[1]] + m.vy[t[2]]) / 3.0;
+        const uint32_t qx = uint32_t(std::lround((cx - x0) * sx)), qy = uint32_t(std::lround((cy - y0) * sy));
+        key[k] = spread(qx) | (spread(qy) << 1);
+    }
+    return key;
+}
+
+// Element order of the device arrays: by level, then instance, then the
+// Morton key of the centroid (ties by local index), so that every level is
+// one contiguous range and face neighbours are mostly close in memory (their
+// face values are then still in the L2 cache when a neighbour gathers them).
 static void sort_elements(dg_solver* h) {
     h->perm.resize(h->K);
     h->inv.resize(h->K);
     h->inst_of.resize(h->K);
+    std::vector<std::vector<int>> order(h->inst.size());
+    for (size_t i = 0; i < h->inst.size(); ++i) {
+        const HostMesh& m = h->inst[i].mesh;
+        const std::vector<uint32_t> key = morton_keys(m);
+        order[i].resize(m.K);
+        for (int k = 0; k < m.K; ++k) order[i][k] = k;
+        std::stable_sort(order[i].begin(), order[i].end(), [&](int a, int b) { return key[a] < key[b]; });
+    }
     int pos = 0;
     h->lev_begin.assign(h->L, 0);
     h->lev_end.assign(h->L, 0);
@@ -174,7 +214,7 @@ static void sort_elements(dg_solver* h) {
         h->lev_begin[l - 1] = pos;
         for (size_t i = 0; i < h->inst.size(); ++i) {
             const Inst& I = h->inst[i];
-            for (int k = 0; k < I.mesh.K; ++k) {
+            for (int k : order[i]) {
                 if (I.mesh.level[k] != l) continue;
                 const int gidx = I.offset + k;
                 h->perm[pos] = gidx;
