@@ -6,8 +6,11 @@ tests/golden/make_golden.py, which calls only the oracle):
   every contraction engine -- the precision study: plain FP32, fused FP32,
   FP32 matrix cores, and the two- and three-part BF16 splits, each reported
   as relative L2 against the oracle;
-* C3, the 496098-triangle graded band mesh with four multi-rate levels, 10
-  coarse steps (80 ticks) of its run, levels compared bit for bit.
+* C3, the 496098-triangle graded band mesh with four multi-rate levels, its
+  configured 100 coarse steps (800 ticks), levels compared bit for bit;
+* C5 with the over-integrated operators (the paper's cubature and Gauss
+  rules), all 64 instances for their 200 steps against the oracle run with
+  the same rules (64 sampled elements per instance).
 
 The launch shape is the one bench.py times (the autotuner's choice)."""
 from __future__ import annotations
@@ -98,3 +101,37 @@ def test_c3_multirate_full_size(path):
     assert eh <= 1e-5 and em <= 1e-5
     assert flips == 0
     assert abs(d["mass"] - float(z["mass"])) <= 1e-6 * float(z["mass"])
+
+
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+def test_c5_overint_full_size(path):
+    _require_gpu()
+    z = _golden("c5_overint")
+    wl = W.c5()
+    Ks = [i.etov.shape[0] for i in wl.instances]
+    log(f"[c5-overint] K={sum(Ks)} path={path}")
+    g = gpu_solver(wl, precision=path, overint=1)
+    g.prepare()
+    g.advance(int(z["steps"]))
+    M = z["mass_matrix"]
+    worst_h = worst_m = 0.0
+    flips = 0
+    for i in range(len(Ks)):
+        idx, J = z["elements"][i], z["J"][i]
+        h, hu, hv = g.get_state(i)
+
+        def nrm(a):
+            return float(np.sum(J * np.einsum("ki,ij,kj->k", a, M, a)))
+
+        eh = np.sqrt(nrm(h[idx] - z["h"][i]) / nrm(z["h"][i]))
+        em = np.sqrt((nrm(hu[idx] - z["hu"][i]) + nrm(hv[idx] - z["hv"][i])) /
+                     (nrm(z["hu"][i]) + nrm(z["hv"][i])))
+        f = g.flags(i)[idx]
+        flips += int(np.sum((f & 3) != z["final_pp"][i])) + int(np.sum(((f >> 2) & 3) != z["final_tvb"][i]))
+        worst_h, worst_m = max(worst_h, eh), max(worst_m, em)
+        d = g.diagnostics(i)
+        assert d["min_depth"] >= 0.0
+        assert abs(d["mass"] - float(z["mass"][i])) <= 1e-6 * float(z["mass"][i])
+        assert eh <= 1e-5 and em <= 1e-5, (i, Ks[i], eh, em)
+    log(f"[c5-overint] {path} 64 instances worst relL2 h={worst_h:.3e} m={worst_m:.3e} flips={flips}")
+    assert flips <= 0.01 * z["elements"].size
