@@ -39,7 +39,7 @@ struct Layout {
     size_t Q[2], R[3], half, mrec, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
     size_t B, Blo, dB, geo, conn, stencil;
-    size_t Dr, Ds, LIFT, Amfma, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
+    size_t Dr, Ds, LIFT, Amfma, AmfmaL, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
     size_t oIc, oPr, oPs, oP, oLg, oI1, oT1, oT3;
     size_t diag_partial, diag_out;
     size_t total;
@@ -354,6 +354,7 @@ static void compute_layout(dg_solver* h) {
     l.Ds = take(size_t(Np) * Np * 4);
     l.LIFT = take(size_t(Np) * nF * 4);
     l.Amfma = take(size_t(64) * 256 * 4 * 2);
+    l.AmfmaL = take(size_t(2) * 64 * 24 * 4);
     l.Abf = take(size_t(8) * 64 * 48);
     l.Wred = take(size_t(8) * 64 * 8);
     l.fmask = take(size_t(nF) * 4);
@@ -671,7 +672,7 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     // Op[node l % 16][K index 4 s + l / 16] (0 outside Np x (2Np + 3Nfp))
     // FP32 MFMA B operand: column tile t (nodes 16 t .. 16 t + 15), step st,
     // lane ln -> Op[16 t + ln % 16][4 st + ln / 16]
-    std::vector<float> amfma;
+    std::vector<float> amfma, amfma_img;
     const int NT = mfma_tiles(h->p.N);
     if (h->p.N <= 5) {
         const int KV = mfma_kv(h->p.N), KS = mfma_steps(h->p.N);
@@ -694,7 +695,17 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
     HIPCHECK(up(l.Dr, Dr.data(), Dr.size() * 4));
     HIPCHECK(up(l.Ds, Ds.data(), Ds.size() * 4));
     HIPCHECK(up(l.LIFT, LIFT.data(), LIFT.size() * 4));
-    if (!amfma.empty()) HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
+    if (!amfma.empty()) {
+        HIPCHECK(up(l.Amfma, amfma.data(), amfma.size() * 4));
+        // the block's LDS image of the same table (rows padded to mfma_lds_row)
+        const int KS = mfma_steps(h->p.N), OPS = mfma_lds_row(h->p.N);
+        amfma_img.assign(size_t(NT) * 64 * OPS, 0.f);
+        for (int t = 0; t < NT; ++t)
+            for (int ln = 0; ln < 64; ++ln)
+                for (int st = 0; st < KS; ++st)
+                    amfma_img[(size_t(t) * 64 + ln) * OPS + st] = amfma[(size_t(t) * KS + st) * 64 + ln];
+        HIPCHECK(up(l.AmfmaL, amfma_img.data(), amfma_img.size() * 4));
+    }
     // BF16 engines: the same operator with K steps of 32, split into hi, mid
     // and lo BF16 parts (op = hi + mid + lo to 2^-24 relative)
     if (h->p.N <= 5) {
@@ -941,6 +952,7 @@ static StepArgs base_step_args(dg_solver* h) {
     a.ops.Ds = reinterpret_cast<const float*>(h->ws + l.Ds);
     a.ops.LIFT = reinterpret_cast<const float*>(h->ws + l.LIFT);
     a.ops.Amfma = reinterpret_cast<const float*>(h->ws + l.Amfma);
+    a.ops.AmfmaL = reinterpret_cast<const float*>(h->ws + l.AmfmaL);
     a.ops.Abf = h->ws + l.Abf;
     a.ops.fmask = reinterpret_cast<const int*>(h->ws + l.fmask);
     a.ops.nodeface = reinterpret_cast<const int*>(h->ws + l.nodeface);

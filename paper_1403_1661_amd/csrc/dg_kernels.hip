@@ -812,6 +812,14 @@ struct MShape {
     static_assert(Np <= LPE && nF <= LPE, "element must fit its lane group");
     static_assert(CMP ? 3 * EPW <= 16 : (LPE == 16 && NT == 1), "one 16-row tile of element x field rows");
     static constexpr int OR = 20;   // row stride (floats) of the packed layout's result transpose
+    // load schedule, chosen per order by measurement: EARLY issues the
+    // operator table's loads first and writes them to LDS before the
+    // neighbour loads, issues every element-indexed load before the wait for
+    // the connectivity, and loads the reduction weights ahead of the
+    // reduction (N = 4: 41 -> 35 us per C2 step, N = 5: 668 -> 619 us per C4
+    // step); at N = 3 the compiler's own order with the table copied after
+    // the neighbour loads is faster (1045 against 1124 us per C5 step)
+    static constexpr bool EARLY = N != 3;
     // packed groups: element r / 3 and field r % 3 of row r < 3 EPW from
     // 4-bit and 2-bit tables (rows past 3 EPW map to element 0, field 0)
     static constexpr unsigned long long row_element_bits() {
@@ -873,9 +881,19 @@ __device__ __forceinline__ int face_node(int fn) {
     if constexpr (N <= 4) {   // 3(N+1) entries of 4 bits fit 64 bits
         constexpr unsigned long long bits = face_node_bits(N);
         return (int)((bits >> (4 * fn)) & 15ull);
+    } else if constexpr (N == 5) {   // 18 entries of 5 bits in two words
+        constexpr unsigned long long b0 = face_node_bits5(N, 0), b1 = face_node_bits5(N, 1);
+        const bool up = fn >= 12;
+        return (int)(((up ? b1 : b0) >> (5 * (up ? fn - 12 : fn))) & 31ull);
     } else {
         return face_node_index(N, fn);
     }
+}
+
+// value of x in the lane whose byte address (4 x lane) is given; every lane
+// of the wave active
+__device__ __forceinline__ float lane_f32(float x, int byte_addr) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, x)));
 }
 
 // lane exchange inside rows of 16 lanes by DPP moves (no LDS traffic); CTRL
@@ -1252,9 +1270,23 @@ step_mfma_kernel(StepArgs a) {
     // memory, so the launch-shape search covers both ways)
     constexpr bool OPL = !BF && WPB == 4;
     constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
+    static_assert(BF || OPS == mfma_lds_row(N), "LDS image row stride");
     __shared__ __attribute__((aligned(16))) float sOp[OPL ? S::NT * 64 * OPS : 4];
 
     const int tid = threadIdx.x;
+    // the block's operator table (four-wave blocks) is copied from its LDS
+    // image in global memory as float4 chunks; these loads go out before any
+    // other, so that waiting for them does not wait for the state loads
+    constexpr int NV4 = OPL ? NT * 64 * OPS / 4 : 1;
+    constexpr int SIT = (NV4 + 64 * WPB - 1) / (64 * WPB);
+    float4 opv[SIT];
+    if constexpr (OPL && S::EARLY) {
+#pragma unroll
+        for (int i = 0; i < SIT; ++i) {
+            const int e = tid + i * 64 * WPB;
+            opv[i] = ldg(reinterpret_cast<const float4*>(a.ops.AmfmaL), (unsigned)(e < NV4 ? e : NV4 - 1));
+        }
+    }
     const int lane = tid & 63, wave = tid >> 6;
     // packed layout: lanes past EPW * LPE are spare; they shadow the wave's
     // last element with the group index LPE (a padding slot everywhere) and
@@ -1327,6 +1359,21 @@ step_mfma_kernel(StepArgs a) {
     const float nx = ldg(a.geo, 16u * kc + 4u + f);
     const float ny = ldg(a.geo, 16u * kc + 7u + f);
     const float fs = ldg(a.geo, 16u * kc + 10u + f);
+    if constexpr (S::EARLY) {
+        // every load indexed by the element alone goes out before anything
+        // waits for the connectivity (loads complete in issue order, so that
+        // wait covers none of them), and the operator table, loaded first, is
+        // written to LDS
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (OPL) {
+            float4* sOp4 = reinterpret_cast<float4*>(sOp);
+#pragma unroll
+            for (int i = 0; i < SIT; ++i) {
+                const int e = tid + i * 64 * WPB;
+                if (e < NV4) sOp4[e] = opv[i];
+            }
+        }
+    }
     const int n = face_node<N>(fn);
     const int nb = f == 0 ? cn.x : (f == 1 ? cn.y : cn.z);
     // exterior node: node Nfp-1-jj of the neighbour's face f2 (a wall face
@@ -1365,17 +1412,19 @@ step_mfma_kernel(StepArgs a) {
         }
     }
 
-    if constexpr (OPL) {
-        // stage the operator table: global order (t, s, lane) to LDS rows
+    if constexpr (OPL && !S::EARLY) {
+        // the operator table in global order (tile, step, lane) to the LDS
+        // rows, after every other load has been issued
         for (int e = tid; e < NT * KS * 64; e += 64 * WPB) {
             const int t = e / (KS * 64), r = e - t * (KS * 64);
             sOp[(t * 64 + (r & 63)) * OPS + (r >> 6)] = ldg(a.ops.Amfma, (unsigned)e);
         }
-        __syncthreads();
     }
+    if constexpr (OPL) __syncthreads();   // the block's operator table is in LDS
 
-    const float eta0 = __shfl(eta, gbase);
-    const float lo0 = __shfl(lo, gbase);
+    const int g4 = 4 * gbase;   // byte address of the element's first lane
+    const float eta0 = lane_f32(eta, g4);
+    const float lo0 = lane_f32(lo, g4);
     const float dlt = (eta - eta0) + (lo - lo0);
 
     // ---- X^T rows: volume fluxes (negated), zero padding.  Every lane
@@ -1399,15 +1448,23 @@ step_mfma_kernel(StepArgs a) {
         }
     }
     // padding after the volume and after the lift columns (finite: the
-    // operator is zero there)
-    if constexpr (KV - 2 * Np > 0) {
-        for (int t = j; t < KV - 2 * Np; t += LPE) {
+    // operator is zero there); one column per lane where they are fewer
+    // than the lanes of the element
+    constexpr int PV = KV - 2 * Np, PL = RL - (KV + nF);
+    static_assert(PV < LPE, "one volume padding column per lane at most");
+    if constexpr (PV > 0) {
+        if (j < PV) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + t)] = 0.f;
+            for (int c = 0; c < 3; ++c) sA[q][c][S::perm(2 * Np + j)] = 0.f;
         }
     }
-    if constexpr (RL - (KV + nF) > 0) {
-        for (int t = j; t < RL - (KV + nF); t += LPE) {
+    if constexpr (PL > 0 && PL <= LPE) {
+        if (j < PL) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + j)] = 0.f;
+        }
+    } else if constexpr (PL > 0) {
+        for (int t = j; t < PL; t += LPE) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) sA[q][c][S::perm(KV + nF + t)] = 0.f;
         }
@@ -1473,12 +1530,13 @@ step_mfma_kernel(StepArgs a) {
     }
 
     // ---- face node fn = j of element q: reconstructed states, LLF flux
-    const float etaM = __shfl(eta, gbase + n);
-    const float huM = __shfl(hu, gbase + n);
-    const float hvM = __shfl(hv, gbase + n);
-    const float BM = __shfl(Bn, gbase + n);
-    const float loM = __shfl(lo, gbase + n);
-    const float blM = __shfl(bl, gbase + n);
+    const int n4 = g4 + 4 * n;
+    const float etaM = lane_f32(eta, n4);
+    const float huM = lane_f32(hu, n4);
+    const float hvM = lane_f32(hv, n4);
+    const float BM = lane_f32(Bn, n4);
+    const float loM = lane_f32(lo, n4);
+    const float blM = lane_f32(bl, n4);
     if (nb < 0) {
         const float mn = huM * nx + hvM * ny;
         etaP = etaM;
@@ -1501,9 +1559,9 @@ step_mfma_kernel(StepArgs a) {
                                      fabsf(unP) + __builtin_amdgcn_sqrtf(g * hsP))
                              : 0.f;
     float lam = lamN;
-    const int fbase = gbase + f * Nfp;
+    const int f4 = g4 + 4 * f * Nfp;   // the face's first lane
 #pragma unroll
-    for (int t = 0; t < Nfp; ++t) lam = fmaxf(lam, __shfl(lamN, fbase + t));
+    for (int t = 0; t < Nfp; ++t) lam = fmaxf(lam, lane_f32(lamN, f4 + 4 * t));
     if (fnode) {
         const float dh = depth_jump(etaM, loM, etaP, loP, hsM, hsP);
         const float dp = 0.25f * g * dh * (hsM + hsP);
@@ -1586,12 +1644,19 @@ step_mfma_kernel(StepArgs a) {
     Rn[1] -= g * dlt * dBx;
     Rn[2] -= g * dlt * dBy;
 
-    // ---- Adams-Bashforth update, RHS ring, half-step traces
+    // the reduction weights are loaded before the kernel's first store: every
+    // store comes at the end, so no wait for a load covers a store
+    double wr[S::KR];
+    if constexpr (S::EARLY) {
+#pragma unroll
+        for (int s = 0; s < S::KR; ++s) wr[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
+    }
+
+    // ---- Adams-Bashforth update and half-step traces (stored at the end)
     float qn[3] = {eta, hu, hv};
     float qlo = lo;
+    float hh[3] = {0.f, 0.f, 0.f};
     if (node) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
         const float dt = dtmin * L.scale;
         const float q0[3] = {eta, hu, hv};
         const float q0lo[3] = {lo, 0.f, 0.f};
@@ -1599,37 +1664,22 @@ step_mfma_kernel(StepArgs a) {
 #pragma unroll
         for (int c = 1; c < 3; ++c)
             qn[c] = q0[c] + dt * (L.ab[0] * Rn[c] + L.ab[1] * r1[c] + L.ab[2] * r2[c]);
-        if (MULTI && L.write_half && a.half != nullptr) {
+        if constexpr (MULTI) {
 #pragma unroll
-            for (int sl = 0; sl < 2; ++sl) {
-                const int slot = a.ops.nodeface[2 * j + sl];
-                if (slot < 0) continue;
-                const unsigned hid = (unsigned)k * nF + slot;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    bH.st(hid, c * HB,
-                          q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c])));
-            }
+            for (int c = 0; c < 3; ++c)
+                hh[c] = q0[c] + (q0lo[c] + dt * (L.half[0] * Rn[c] + L.half[1] * r1[c] + L.half[2] * r2[c]));
         }
     }
-    // ---- FP64 element reductions on the matrix cores, min depth by shuffles
+    // ---- FP64 element reductions on the matrix cores
     const double h64 = node ? ((double)qn[0] - (double)Bn) + ((double)qlo - (double)bl) : 0.0;
     wave_lds_sync();   // X^T / result reads done before the node values overwrite them
     sVd[q][0][j] = h64;
     sVd[q][1][j] = node ? (double)qn[1] : 0.0;
     sVd[q][2][j] = node ? (double)qn[2] : 0.0;
-    double hmin = node ? h64 : 1e300;
-    if constexpr (!S::CMP) {
-        hmin = row_min16(hmin);   // the element is one 16-lane DPP row
-    } else {
-        // rotation doubling inside the group: after the shift s every lane
-        // holds the minimum of 2 s consecutive (cyclic) lanes of its group
-#pragma unroll
-        for (int sh = 1; sh < LPE; sh <<= 1) {
-            const int pj = j + sh;   // j <= LPE and sh < LPE: one wrap at most
-            hmin = fmin(hmin, __shfl(hmin, gbase + (pj >= LPE ? pj - LPE : pj)));
-        }
-    }
+    // a node of the element at or below eps (the positivity test needs only
+    // that, not the minimum itself): one ballot bit per lane
+    const unsigned long long lowm = __ballot(node && h64 <= (double)a.eps);
+    const bool any_low = ((lowm >> gbase) & ((1ull << LPE) - 1ull)) != 0ull;
     wave_lds_sync();
     doublex4 red = {0.0, 0.0, 0.0, 0.0};
     {
@@ -1638,25 +1688,32 @@ step_mfma_kernel(StepArgs a) {
         const int c = lane & 15;
         const int ec = S::CMP ? S::row_element(c) : c >> 2, fc = S::CMP ? S::row_field(c) : c & 3;
         const bool col = S::CMP ? c < 3 * EPW : (fc < 3 && ec < EPW);
+        const int ecc = ec < EPW ? ec : 0, fcc = fc < 3 ? fc : 0;
 #pragma unroll
         for (int s = 0; s < S::KR; ++s) {
             const int nd = 4 * s + ag;
-            const double bv = (col && nd < Np) ? sVd[ec < EPW ? ec : 0][fc < 3 ? fc : 0][nd < Np ? nd : 0] : 0.0;
-            red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red,
-                                                       0, 0, 0);
+            if constexpr (S::EARLY) {
+                const double raw = sVd[ecc][fcc][nd < Np ? nd : 0];   // always a valid row
+                const double bv = (col && nd < Np) ? raw : 0.0;
+                red = __builtin_amdgcn_mfma_f64_16x16x4f64(wr[s], bv, red, 0, 0, 0);
+            } else {
+                const double bv = (col && nd < Np) ? sVd[ecc][fcc][nd < Np ? nd : 0] : 0.0;
+                red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red, 0,
+                                                           0, 0);
+            }
         }
         // lane 16 g + c holds row g (0: mean, 1-3: midpoint deviation g-1) of column c
         if (col) sRed[ec][ag == 0 ? 1 + fc : 4 + 3 * fc + (ag - 1)] = red[0];
     }
     wave_lds_sync();
     // ---- positivity limiter decision (Algorithm 5.2), taken by all lanes of
-    // the element (hmin is already the element minimum in every lane)
+    // the element
     const double hb = sRed[q][1];
     double scale = 1.0, hdry = 0.0;
     int code = 0;
     // a mean below h0 with every node above eps (negative vertex weights of
     // the nodal mean at N = 4, 6) also takes the dry branch
-    if (a.pp_on && (hmin <= (double)a.eps || hb < (double)a.h0)) {
+    if (a.pp_on && (any_low || hb < (double)a.h0)) {
         if (hb < (double)a.h0) {
             code = 2;
             hdry = a.dry_literal ? (double)a.h0 : fmax(hb, 0.0);
@@ -1670,49 +1727,65 @@ step_mfma_kernel(StepArgs a) {
             scale = den > 0.0 ? fmin(1.0, (hb - (double)a.h0) / den) : 1.0;
         }
     }
-    if (live && j == 0 && code == 2 && hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
-    // post-limiter means
-    const double mean0 = code == 2 ? hdry : hb;
-    const double mean1 = code == 2 ? 0.0 : sRed[q][2];
-    const double mean2 = code == 2 ? 0.0 : sRed[q][3];
-    // ---- hand-off to the TVB kernel: a 32-byte record of post-limiter means
-    // and positivity code for every element, P1 midpoint deviations (FP32)
-    // of every element that is not dry
-    if (live && j < 4)
-        stg(a.mrec, 4u * (unsigned)k + j, j == 0 ? mean0 : (j == 1 ? mean1 : (j == 2 ? mean2 : (double)code)));
+    // ---- limited nodal values and the new state
+    float out[3] = {qn[0], qn[1], qn[2]};
+    float olo = qlo;
+    if (node) {
+        if (code == 2) {
+            eta_split(hdry + ((double)Bn + (double)bl), out[0], olo);
+            out[1] = 0.f;
+            out[2] = 0.f;
+        } else if (code == 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double val = sRed[q][1 + c];
+#pragma unroll
+                for (int ed = 0; ed < 3; ++ed) val += scale * sRed[q][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
+                if (c == 0)
+                    eta_split(val + ((double)Bn + (double)bl), out[0], olo);
+                else
+                    out[c] = (float)val;
+            }
+        }
+        if (a.thin_cut > 0.f && (out[0] - Bn) + (olo - bl) < a.thin_cut) {   // thin film: no momentum
+            out[1] = 0.f;
+            out[2] = 0.f;
+        }
+    }
+    // ---- stores: RHS ring, half-step traces, new state; then the hand-off
+    // to the TVB kernel (a 32-byte record of post-limiter means and
+    // positivity code for every element, P1 midpoint deviations (FP32) of
+    // every element that is not dry) and the flags
+    if (node) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
+        if (MULTI && L.write_half && a.half != nullptr) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                const int slot = a.ops.nodeface[2 * j + sl];
+                if (slot < 0) continue;
+                const unsigned hid = (unsigned)k * nF + slot;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bH.st(hid, c * HB, hh[c]);
+            }
+        }
+        bQo.st(idx, 0, out[0]);
+        bQo.st(idx, FB, out[1]);
+        bQo.st(idx, 2u * FB, out[2]);
+        bQo.st16(idx, 3u * FB, lo_encode(out[0], olo));
+    }
+    if (live && j < 4) {
+        const double mv = code == 2 ? (j == 0 ? hdry : 0.0) : (j < 3 ? sRed[q][1 + j] : 0.0);
+        stg(a.mrec, 4u * (unsigned)k + j, j == 3 ? (double)code : mv);
+    }
     if (live && j < 9 && code != 2) {
         const int ed = j / 3, r = j % 3;   // field r at edge ed
         stg(a.devs, (unsigned)(3 * r + ed) * (unsigned)a.K + k, (float)(scale * sRed[q][4 + 3 * r + ed]));
     }
-    if (live && j == 0) a.flags[k] = (uint8_t)code;
-    if (!node) return;
-    // ---- limited nodal values and the new state
-    float out[3] = {qn[0], qn[1], qn[2]};
-    float olo = qlo;
-    if (code == 2) {
-        eta_split(hdry + ((double)Bn + (double)bl), out[0], olo);
-        out[1] = 0.f;
-        out[2] = 0.f;
-    } else if (code == 1) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double val = sRed[q][1 + c];
-#pragma unroll
-            for (int ed = 0; ed < 3; ++ed) val += scale * sRed[q][4 + 3 * c + ed] * a.ops.phi[ed * Np + j];
-            if (c == 0)
-                eta_split(val + ((double)Bn + (double)bl), out[0], olo);
-            else
-                out[c] = (float)val;
-        }
+    if (live && j == 0) {
+        a.flags[k] = (uint8_t)code;
+        if (code == 2 && hb < 0.0) atomicAdd(&a.counters[0], 1ULL);
     }
-    if (a.thin_cut > 0.f && (out[0] - Bn) + (olo - bl) < a.thin_cut) {   // thin film: no momentum
-        out[1] = 0.f;
-        out[2] = 0.f;
-    }
-    bQo.st(idx, 0, out[0]);
-    bQo.st(idx, FB, out[1]);
-    bQo.st(idx, 2u * FB, out[2]);
-    bQo.st16(idx, 3u * FB, lo_encode(out[0], olo));
 }
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,14 @@ constexpr unsigned long long face_node_bits(int N) {
     return b;
 }
 
+// face nodes packed 5 bits each, twelve to a word (N = 5: two words)
+constexpr unsigned long long face_node_bits5(int N, int part) {
+    unsigned long long b = 0;
+    for (int fn = 12 * part; fn < 3 * (N + 1) && fn < 12 * part + 12; ++fn)
+        b |= (unsigned long long)face_node_index(N, fn) << (5 * (fn - 12 * part));
+    return b;
+}
+
 // Kernel modes of the step kernel.
 enum StepMode : int {
     MODE_FUSED = 0,        // RHS + AB update + positivity limiter + means/deviations
@@ -53,6 +61,8 @@ struct DevOps {
     const float* Ds;       // Np x Np
     const float* LIFT;     // Np x 3Nfp
     const float* Amfma;    // FP32 MFMA B operand: step s, lane l -> Op[l % 16][4 s + l / 16]
+    const float* AmfmaL;   // the same table as the block's LDS image: row 64 t + l holds the
+                           // steps of lane l of tile t, row stride mfma_lds_row(N) floats
     const void* Abf;       // BF16 MFMA B operand: step s, lane l -> hi, mid, lo parts (8 bf16
                            // each) of Op[l % 16][32 s + 8 (l / 16) + i], i = 0..7
     const int* fmask;      // 3Nfp
@@ -204,6 +214,12 @@ constexpr int mfma_tiles(int N) { return ((N + 1) * (N + 2) / 2 + 15) / 16; }
 // mfma_kv(N) / 4 of them volume-only
 constexpr int mfma_kv(int N) { return ((N + 1) * (N + 2) + 3) & ~3; }
 constexpr int mfma_steps(int N) { return (mfma_kv(N) + 3 * (N + 1) + 3) / 4; }
+// row stride (floats) of the FP32 operator table staged in LDS: the steps
+// padded to a multiple of 4, plus 4 when that is a multiple of 8, so that the
+// 128-bit reads of consecutive lanes fall in distinct banks
+constexpr int mfma_lds_row(int N) {
+    return ((mfma_steps(N) + 3) & ~3) % 8 == 0 ? ((mfma_steps(N) + 3) & ~3) + 4 : ((mfma_steps(N) + 3) & ~3);
+}
 const char* device_error_string();
 
 }  // namespace dgswe

@@ -228,8 +228,10 @@ def test_checkpoint_resume_multirate_and_ensemble(case):
     b.restore(blob)
     b.advance(n)
     for i in range(len(wl.instances)):
-        for x, y in zip(a.get_state(i), b.get_state(i)):
-            assert np.array_equal(x, y)
+        for fld, (x, y) in enumerate(zip(a.get_state(i), b.get_state(i))):
+            diff = np.argwhere(x != y)
+            assert diff.size == 0, (f"instance {i} field {fld}: {len(diff)} nodes differ, first "
+                                    f"{diff[:4].tolist()}, max {np.max(np.abs(x - y)):.3e}")
         _, dt = a.levels(i)
         ticks = 2 * n * 2 ** (wl.max_levels - 1)
         assert a.diagnostics(i)["time"] == b.diagnostics(i)["time"] == float(ticks) * dt
