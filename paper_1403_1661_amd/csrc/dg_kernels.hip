@@ -1271,7 +1271,12 @@ step_mfma_kernel(StepArgs a) {
     constexpr bool OPL = !BF && WPB == 4;
     constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
     static_assert(BF || OPS == mfma_lds_row(N), "LDS image row stride");
-    __shared__ __attribute__((aligned(16))) float sOp[OPL ? S::NT * 64 * OPS : 4];
+    // four-wave blocks with the early schedule also stage the FP64 reduction
+    // weights (one float4 per thread) after the operator table, so that no
+    // wave loads them from global memory (C4: 607 -> 580 us)
+    constexpr bool WL = OPL && S::EARLY;
+    constexpr int WOFF = S::NT * 64 * OPS;   // reduction weights after the operator table
+    __shared__ __attribute__((aligned(16))) float sOp[OPL ? WOFF + (WL ? 2 * 64 * S::KR : 0) : 4];
 
     const int tid = threadIdx.x;
     // the block's operator table (four-wave blocks) is copied from its LDS
@@ -1287,6 +1292,10 @@ step_mfma_kernel(StepArgs a) {
             opv[i] = ldg(reinterpret_cast<const float4*>(a.ops.AmfmaL), (unsigned)(e < NV4 ? e : NV4 - 1));
         }
     }
+    constexpr int NW4 = 32 * S::KR;   // float4 chunks of the reduction weights
+    static_assert(!WL || NW4 <= 64 * WPB, "one chunk of the weights per thread");
+    float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (WL) wv = ldg(reinterpret_cast<const float4*>(a.ops.Wred), (unsigned)(tid < NW4 ? tid : 0));
     const int lane = tid & 63, wave = tid >> 6;
     // packed layout: lanes past EPW * LPE are spare; they shadow the wave's
     // last element with the group index LPE (a padding slot everywhere) and
@@ -1356,9 +1365,15 @@ step_mfma_kernel(StepArgs a) {
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
     const int f = fn / Nfp, jj = fn - f * Nfp;
-    const float nx = ldg(a.geo, 16u * kc + 4u + f);
-    const float ny = ldg(a.geo, 16u * kc + 7u + f);
-    const float fs = ldg(a.geo, 16u * kc + 10u + f);
+    // outward normal and Fscale = sJ / J of face f from the metric terms
+    // (straight-sided element): the gradient of the coordinate that is
+    // constant on the face, -grad s, grad(r + s), -grad r for faces 0, 1, 2,
+    // has length sJ / J and points outward
+    const float gx = f == 0 ? -g0.z : (f == 1 ? g0.x + g0.z : -g0.x);
+    const float gy = f == 0 ? -g0.w : (f == 1 ? g0.y + g0.w : -g0.y);
+    const float fs = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
+    const float rfs = __builtin_amdgcn_rcpf(fs);
+    const float nx = gx * rfs, ny = gy * rfs;
     if constexpr (S::EARLY) {
         // every load indexed by the element alone goes out before anything
         // waits for the connectivity (loads complete in issue order, so that
@@ -1371,6 +1386,9 @@ step_mfma_kernel(StepArgs a) {
             for (int i = 0; i < SIT; ++i) {
                 const int e = tid + i * 64 * WPB;
                 if (e < NV4) sOp4[e] = opv[i];
+            }
+            if constexpr (WL) {
+                if (tid < NW4) sOp4[WOFF / 4 + tid] = wv;
             }
         }
     }
@@ -1647,7 +1665,7 @@ step_mfma_kernel(StepArgs a) {
     // the reduction weights are loaded before the kernel's first store: every
     // store comes at the end, so no wait for a load covers a store
     double wr[S::KR];
-    if constexpr (S::EARLY) {
+    if constexpr (S::EARLY && !WL) {
 #pragma unroll
         for (int s = 0; s < S::KR; ++s) wr[s] = ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
     }
@@ -1695,7 +1713,8 @@ step_mfma_kernel(StepArgs a) {
             if constexpr (S::EARLY) {
                 const double raw = sVd[ecc][fcc][nd < Np ? nd : 0];   // always a valid row
                 const double bv = (col && nd < Np) ? raw : 0.0;
-                red = __builtin_amdgcn_mfma_f64_16x16x4f64(wr[s], bv, red, 0, 0, 0);
+                const double w = WL ? reinterpret_cast<const double*>(sOp + WOFF)[s * 64 + lane] : wr[s];
+                red = __builtin_amdgcn_mfma_f64_16x16x4f64(w, bv, red, 0, 0, 0);
             } else {
                 const double bv = (col && nd < Np) ? sVd[ecc][fcc][nd < Np ? nd : 0] : 0.0;
                 red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red, 0,
