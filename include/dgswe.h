@@ -146,7 +146,11 @@ int32_t dg_default_params(int32_t N, dg_params* p);
 int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p,
                   dg_solver** out);
 
-/* Release the handle (not the caller's device buffer).  NULL is a no-op. */
+/* Release the handle (not the caller's device buffer).  NULL is a no-op.
+ * Waits first for the work the solver queued on its own stream (graph
+ * replays of dg_advance), so that the caller may free or reuse the device
+ * buffer as soon as this returns; work queued on the caller's stream is
+ * ordered by that stream as usual. */
 void dg_destroy(dg_solver* h);
 
 /* Message of the last failed call on this thread ("" if none). */

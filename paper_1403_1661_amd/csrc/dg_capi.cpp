@@ -536,6 +536,16 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
 
 void dg_destroy(dg_solver* h) {
     if (!h) return;
+    // graph replays may still be running on the solver's own stream and
+    // writing into the caller's buffer: finish them before the caller can
+    // free or reuse that memory (and before their executable goes away)
+    if (h->exec) {
+        int cur = -1;
+        const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != h->device;
+        if (switch_dev) (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->exec);
+        if (switch_dev) (void)hipSetDevice(cur);
+    }
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     for (auto* v : {&h->prof_events, &h->prof_tvb_events})
         for (auto& ev : *v) {
