@@ -110,9 +110,10 @@ typedef struct dg_params {
     int32_t dry_literal;    /* 1: dry element gets h = h0 (Algorithm 5.2 as printed); */
                             /* 0: h = max(mean, 0), which conserves mass              */
     int32_t use_graph;      /* 1: replay dg_advance steps from a captured hipGraph    */
-    int32_t elems_per_block;/* 0 = default for N and path; matrix-core paths: 1, 2 or */
-                            /* 4 waves of 64/lanes elements (N = 1, 2, 4: 4, 8, 16;   */
-                            /* N = 3: 5, 10, 20; N = 5: 3, 6, 12); VALU paths:        */
+    int32_t elems_per_block;/* 0 = default for N and path; matrix-core paths: 1, 2, 4 */
+                            /* or 8 waves of 64/lanes elements (N = 1, 2, 4: 4, 8,    */
+                            /* 16, 32; N = 3: 5, 10, 20, 40; N = 5: 3, 6, 12, 24),    */
+                            /* default 4 waves (8 at N = 5); VALU paths:              */
                             /* floor(256 / Np); anything else is DG_EINVAL            */
     double thin_cut;        /* >= 0; > 0: after the limiters, momentum is set to zero */
                             /* at nodes whose depth is below thin_cut (thin films at  */
@@ -207,7 +208,7 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 
 /* Autotuner (launch shape of the step kernel).  Times the step kernel of
  * the next tick `reps` times for each elements-per-block candidate of the
- * path (matrix-core paths: 1, 2 and 4 waves, see elems_per_block; the VALU
+ * path (matrix-core paths: 1, 2, 4 and 8 waves, see elems_per_block; the VALU
  * paths have one shape) and
  * keeps the fastest in the solver's parameters.  The state, history, flags
  * and counters are left as they were.  Writes min(max_out, candidates) pairs (elements per

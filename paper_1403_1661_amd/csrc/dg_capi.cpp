@@ -436,10 +436,11 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
         const int valu_e = 256 / ((p->N + 1) * (p->N + 2) / 2);
         const int epw = 64 / mfma_lanes(p->N);
         const int e = p->elems_per_block;
-        const bool ok = mfma ? (e == epw || e == 2 * epw || e == 4 * epw) : e == valu_e;
+        const bool ok = mfma ? (e == epw || e == 2 * epw || e == 4 * epw || e == 8 * epw) : e == valu_e;
         if (!ok)
-            return fail(DG_EINVAL, mfma ? "elems_per_block must be 0 or 1, 2, 4 waves of 64/lanes elements on "
-                                          "the MFMA paths (N = 1, 2, 4: 4, 8, 16; N = 3: 5, 10, 20; N = 5: 3, 6, 12)"
+            return fail(DG_EINVAL, mfma ? "elems_per_block must be 0 or 1, 2, 4, 8 waves of 64/lanes elements on "
+                                          "the MFMA paths (N = 1, 2, 4: 4, 8, 16, 32; N = 3: 5, 10, 20, 40; "
+                                          "N = 5: 3, 6, 12, 24)"
                                         : "elems_per_block must be 0 or floor(256 / Np) on the VALU paths");
     }
     std::unique_ptr<dg_solver> h;
@@ -1461,7 +1462,7 @@ int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out,
     std::vector<int> cand;
     if (h->p.precision >= DG_FUSED_MFMA32) {
         const int epw = 64 / mfma_lanes(h->p.N);
-        cand = {epw, 2 * epw, 4 * epw};
+        cand = {epw, 2 * epw, 4 * epw, 8 * epw};
     }
     else
         cand = {step_elems_per_block(h->p.N, engine_of(h->p.precision))};

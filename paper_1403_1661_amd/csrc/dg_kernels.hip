@@ -1266,9 +1266,9 @@ step_mfma_kernel(StepArgs a) {
     // FP32 operator table of the block: lane l of tile t reads its KS steps
     // as float4 chunks from row t * 64 + l (row stride padded so that the
     // 128-bit reads of consecutive lanes fall in distinct banks)
-    // (blocks of four waves; smaller blocks read the table from global
+    // (blocks of four or eight waves; smaller blocks read the table from global
     // memory, so the launch-shape search covers both ways)
-    constexpr bool OPL = !BF && WPB == 4;
+    constexpr bool OPL = !BF && WPB >= 4;
     constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
     static_assert(BF || OPS == mfma_lds_row(N), "LDS image row stride");
     // four-wave blocks with the early schedule also stage the FP64 reduction
@@ -2034,7 +2034,7 @@ static int check_launch(const char* what) {
 }
 
 int step_elems_per_block(int N, int engine) {
-    if (engine != ENGINE_VALU && N <= 5) return kMfmaDefaultWaves * (64 / mfma_lanes(N));
+    if (engine != ENGINE_VALU && N <= 5) return mfma_default_waves(N) * (64 / mfma_lanes(N));
     return 256 / ((N + 1) * (N + 2) / 2);
 }
 
@@ -2105,9 +2105,10 @@ static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e
                 case 1: if (dispatch_mfma<N, 1>(n, s, a, e0, e1)) return -1; break;
                 case 2: if (dispatch_mfma<N, 2>(n, s, a, e0, e1)) return -1; break;
                 case 4: if (dispatch_mfma<N, 4>(n, s, a, e0, e1)) return -1; break;
+                case 8: if (dispatch_mfma<N, 8>(n, s, a, e0, e1)) return -1; break;
                 default:
                     std::snprintf(g_dev_err, sizeof(g_dev_err),
-                                  "elements per block %d is not 1, 2 or 4 waves of %d elements", epb, EPW);
+                                  "elements per block %d is not 1, 2, 4 or 8 waves of %d elements", epb, EPW);
                     return -1;
             }
             return check_launch("step mfma kernel");

@@ -153,9 +153,9 @@ def test_error_paths():
         dgswe.Solver([(vx, vy, np.array([[0, 1, 2]]))], 2, tvb_nu=0.5)
     assert e.value.code == -1
     tri = np.array([[0, 1, 2]])
-    for epb in (5, 10, 20):   # launch shapes of the matrix-core kernel (12-lane groups at N = 3)
+    for epb in (5, 10, 20, 40):   # launch shapes of the matrix-core kernel (12-lane groups at N = 3)
         dgswe.Solver([(vx, vy, tri)], 3, precision="fused_mfma32", elems_per_block=epb)
-    for epb in (4, 8, 16):   # 16-lane groups at N = 4
+    for epb in (4, 8, 16, 32):   # 16-lane groups at N = 4
         dgswe.Solver([(vx, vy, tri)], 4, precision="fused_mfma32", elems_per_block=epb)
     for bad, prec in ((12, "fused_mfma32"), (4, "fused_mfma32"), (16, "fused_fp32"), (-4, "fused_mfma32")):
         with pytest.raises(dgswe.DGError) as e:
@@ -165,7 +165,8 @@ def test_error_paths():
     for prec in ("fused_mfma32", "fused_bf16x3", "fused_bf16x6"):   # matrix cores: N <= 5
         dgswe.Solver([(vx, vy, tri)], 5, precision=prec)
         dgswe.Solver([(vx, vy, tri)], 5, precision=prec, elems_per_block=3)   # 21-lane elements
-        for bad in (2, 16):
+        dgswe.Solver([(vx, vy, tri)], 5, precision=prec, elems_per_block=24)
+        for bad in (2, 16, 48):
             with pytest.raises(dgswe.DGError) as e:
                 dgswe.Solver([(vx, vy, tri)], 5, precision=prec, elems_per_block=bad)
             assert e.value.code == -1

@@ -204,12 +204,12 @@ def test_near_dry_front(path, N):
 
 def test_multirate_block_shapes_bitwise():
     """The multi-rate launch cuts each level's element range into whole
-    blocks; 1, 2 or 4 waves per block change only that cut, so the MRAB
+    blocks; 1, 2, 4 or 8 waves per block change only that cut, so the MRAB
     trajectories agree bit for bit."""
     _require_gpu()
     wl = W.c3(n0=2)
     runs = []
-    for epb in (5, 10, 20):   # N = 3: five 12-lane elements per wave
+    for epb in (5, 10, 20, 40):   # N = 3: five 12-lane elements per wave
         g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
         g.advance(5)
         runs.append(g.get_state(0))

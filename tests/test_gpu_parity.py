@@ -306,7 +306,7 @@ def test_bench_config_500_steps(path):
 
 
 def test_block_shapes_and_autotune_bitwise():
-    """Elements per block (4, 8, 16) only changes the launch shape of the
+    """Elements per block (4, 8, 16, 32) only changes the launch shape of the
     matrix-core kernel: every element's arithmetic is wave-local, so the
     trajectories agree bit for bit; the autotuner's trial launches leave the
     state, flags and counters as the next step expects them."""
@@ -316,7 +316,7 @@ def test_block_shapes_and_autotune_bitwise():
     ref = gpu_solver(wl, precision="fused_mfma32", elems_per_block=16)
     ref.advance(30)
     want = ref.get_state(0)
-    for epb in (4, 8):
+    for epb in (4, 8, 32):
         g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
         g.advance(30)
         for x, y in zip(g.get_state(0), want):
@@ -327,7 +327,7 @@ def test_block_shapes_and_autotune_bitwise():
     d0 = t.diagnostics(0)
     res = t.autotune(reps=3)
     log(f"[block-shapes] autotune {res}")
-    assert sorted(e for e, _ in res) == [4, 8, 16] and all(us > 0 for _, us in res)
+    assert sorted(e for e, _ in res) == [4, 8, 16, 32] and all(us > 0 for _, us in res)
     assert np.array_equal(t.flags(0), f0)
     assert t.diagnostics(0)["negative_means"] == d0["negative_means"]
     t.advance(23)
@@ -413,8 +413,8 @@ def test_degree5_reduced_c4(path):
 
 def test_degree5_bf16x3_and_block_shapes():
     """N = 5 with the two-part BF16 split (its own tolerance) and the three
-    launch shapes of the 21-lane kernel (3, 6, 12 elements per block), which
-    agree bit for bit."""
+    launch shapes of the 21-lane kernel (3, 6, 12, 24 elements per block),
+    which agree bit for bit."""
     _require_gpu()
     _compare("c4-small-bf16x3", W.c4(nx=128, ny=64), 30, precision="fused_bf16x3", tol=BF16_TOL,
              tol_m=BF16_TOL)
@@ -422,7 +422,7 @@ def test_degree5_bf16x3_and_block_shapes():
     ref = gpu_solver(wl, precision="fused_mfma32", elems_per_block=12)
     ref.advance(12)
     want = ref.get_state(0)
-    for epb in (3, 6):
+    for epb in (3, 6, 24):
         g = gpu_solver(wl, precision="fused_mfma32", elems_per_block=epb)
         g.advance(12)
         for x, y in zip(g.get_state(0), want):
