@@ -1241,7 +1241,11 @@ constexpr int mfma_waves_target(int N, bool multi, int bf) {
     return (bf == 2 ? (multi ? 4 : 5) : (bf ? (multi ? 5 : 6) : (multi ? 6 : 7))) - (N == 5 ? 1 : 0);
 }
 
-template <int N, bool MULTI, int WPB, int BF>
+// UPD: the update alone (MODE_UPDATE_ONLY of the over-integrated form): the
+// right-hand side is read from the ring slot another kernel wrote, and the
+// AB update, the FP64 reductions, the positivity limiter and the hand-off to
+// the TVB kernel run as in the fused kernel
+template <int N, bool MULTI, int WPB, int BF, bool UPD = false>
 __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(mfma_waves_target(N, MULTI, BF), 8)))
 step_mfma_kernel(StepArgs a) {
     using S = MShape<N, BF>;
@@ -1268,7 +1272,7 @@ step_mfma_kernel(StepArgs a) {
     // 128-bit reads of consecutive lanes fall in distinct banks)
     // (blocks of four or eight waves; smaller blocks read the table from global
     // memory, so the launch-shape search covers both ways)
-    constexpr bool OPL = !BF && WPB >= 4;
+    constexpr bool OPL = !BF && WPB >= 4 && !UPD;
     constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
     static_assert(BF || OPS == mfma_lds_row(N), "LDS image row stride");
     // four-wave blocks with the early schedule also stage the FP64 reduction
@@ -1353,8 +1357,8 @@ step_mfma_kernel(StepArgs a) {
     const float lo = lo_decode(eta, bQi.ld16(idx, 3u * FB));
     const float Bn = bB.ld(idx, 0);
     const float bl = lo_decode(Bn, bBl.ld16(idx, 0));
-    const float dBx = bdB.ld(idx, 0);   // static bed gradient
-    const float dBy = bdB.ld(idx, FB);
+    const float dBx = UPD ? 0.f : bdB.ld(idx, 0);   // static bed gradient
+    const float dBy = UPD ? 0.f : bdB.ld(idx, FB);
     // the RHS history is read unconditionally (slots hold zeros or finite RHS
     // values) and weighted by the level's AB coefficients
 #pragma unroll
@@ -1362,6 +1366,14 @@ step_mfma_kernel(StepArgs a) {
         r1[c] = bR1.ld(idx, c * FB);
         r2[c] = bR2.ld(idx, c * FB);
     }
+    const int ag = lane >> 4;   // K group supplied by this lane (contraction, reductions)
+    const unsigned HB = 4u * (unsigned)a.KnF;   // bytes of one half-trace field
+    const BufF32 bH(a.half, 3u * HB);
+    float Rn[3];
+    if constexpr (UPD) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Rn[c] = bR0.ld(idx, c * FB);
+    } else {
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
     const int f = fn / Nfp, jj = fn - f * Nfp;
@@ -1402,8 +1414,6 @@ step_mfma_kernel(StepArgs a) {
     float BP = bB.ld(id2, 0);
     float blP = lo_decode(BP, bBl.ld16(id2, 0));
     float etaP, huP, hvP, loP = 0.f;
-    const unsigned HB = 4u * (unsigned)a.KnF;   // bytes of one half-trace field
-    const BufF32 bH(a.half, 3u * HB);
     if constexpr (!MULTI) {
         etaP = bQi.ld(id2, 0);
         huP = bQi.ld(id2, FB);
@@ -1498,7 +1508,6 @@ step_mfma_kernel(StepArgs a) {
     const int ar = lane & 15;
     const int ae = S::CMP ? S::row_element(ar) : (ar >> 2);
     const int arow = S::CMP ? S::row_field(ar) : ((ar & 3) == 3 ? 0 : (ar & 3));
-    const int ag = lane >> 4;           // K group supplied by this lane
     floatx4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -1640,7 +1649,6 @@ step_mfma_kernel(StepArgs a) {
             }
         }
     }
-    float Rn[3];
     if constexpr (!S::CMP) {   // the lane of node j holds rows 4 q .. 4 q + 2 of column j
         Rn[0] = acc[0][0];
         Rn[1] = acc[0][1];
@@ -1661,6 +1669,7 @@ step_mfma_kernel(StepArgs a) {
     }
     Rn[1] -= g * dlt * dBx;
     Rn[2] -= g * dlt * dBy;
+    }   // right-hand side (fused kernel)
 
     // the reduction weights are loaded before the kernel's first store: every
     // store comes at the end, so no wait for a load covers a store
@@ -1777,7 +1786,8 @@ step_mfma_kernel(StepArgs a) {
     // every element that is not dry) and the flags
     if (node) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bR0.st(idx, c * FB, Rn[c]);
+        for (int c = 0; c < 3; ++c)
+            if constexpr (!UPD) bR0.st(idx, c * FB, Rn[c]);
         if (MULTI && L.write_half && a.half != nullptr) {
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
@@ -2050,7 +2060,7 @@ static void dispatch(K kernel, int blocks, int threads, hipStream_t s, const Ste
 }
 
 // matrix-core step kernel with W waves (EPW W elements) per block
-template <int N, int W>
+template <int N, int W, bool UPD = false>
 static int dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0, hipEvent_t e1) {
     constexpr int EPW = 64 / mfma_lanes(N), EPB = EPW * W;
     const int bf = a.engine == ENGINE_MFMA_BF16X3 ? 1 : (a.engine == ENGINE_MFMA_BF16X6 ? 2 : 0);
@@ -2081,12 +2091,14 @@ static int dispatch_mfma(int n, hipStream_t s, const StepArgs& a, hipEvent_t e0,
             return -1;
         }
         m.q_pair_bytes = (unsigned)qd;
-        if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, m, e0, e1);
+        if constexpr (UPD) dispatch(step_mfma_kernel<N, true, W, 0, true>, blocks, 64 * W, s, m, e0, e1);
+        else if (bf == 1) dispatch(step_mfma_kernel<N, true, W, 1>, blocks, 64 * W, s, m, e0, e1);
         else if (bf == 2) dispatch(step_mfma_kernel<N, true, W, 2>, blocks, 64 * W, s, m, e0, e1);
         else dispatch(step_mfma_kernel<N, true, W, 0>, blocks, 64 * W, s, m, e0, e1);
     } else {
         const int blocks = (n + EPB - 1) / EPB;
-        if (bf == 1) dispatch(step_mfma_kernel<N, false, W, 1>, blocks, 64 * W, s, a, e0, e1);
+        if constexpr (UPD) dispatch(step_mfma_kernel<N, false, W, 0, true>, blocks, 64 * W, s, a, e0, e1);
+        else if (bf == 1) dispatch(step_mfma_kernel<N, false, W, 1>, blocks, 64 * W, s, a, e0, e1);
         else if (bf == 2) dispatch(step_mfma_kernel<N, false, W, 2>, blocks, 64 * W, s, a, e0, e1);
         else dispatch(step_mfma_kernel<N, false, W, 0>, blocks, 64 * W, s, a, e0, e1);
     }
@@ -2098,6 +2110,11 @@ static int launch_step_n(const StepArgs& a, hipStream_t s, int epb, hipEvent_t e
     const int n = a.k_end - a.k_begin;
     if (n <= 0) return 0;
     if constexpr (N <= 5) {
+        if (a.engine == ENGINE_MFMA_F32 && a.mode == MODE_UPDATE_ONLY) {
+            // the over-integrated form's update on the matrix-core kernel
+            if (dispatch_mfma<N, 4, true>(n, s, a, e0, e1)) return -1;
+            return check_launch("update mfma kernel");
+        }
         if (a.engine != ENGINE_VALU && a.mode == MODE_FUSED) {
             constexpr int EPW = 64 / mfma_lanes(N);
             const int w = epb % EPW == 0 ? epb / EPW : 0;

@@ -158,6 +158,30 @@ def test_graph_replay_matches_eager(path):
             assert np.array_equal(x, y)
 
 
+def test_destroy_waits_for_queued_replays():
+    """A solver dropped right after dg_advance queued its graph replays on its
+    own stream: dg_destroy waits for them, so a solver that then reuses the
+    freed workspace runs undisturbed (bit for bit equal to a reference run)."""
+    _require_gpu()
+    import gc
+    wl = W.small_wetdry(n=24, N=4)
+    log("[destroy-in-flight]")
+    ref = gpu_solver(wl, precision="fused_mfma32")
+    ref.advance(12)
+    want = ref.get_state(0)
+    del ref
+    gc.collect()
+    for _ in range(3):
+        a = gpu_solver(wl, precision="fused_mfma32")
+        a.advance(60)    # replays queued on the solver's own stream, not waited for here
+        del a            # destroyed with them in flight; the workspace goes back to torch
+        b = gpu_solver(wl, precision="fused_mfma32")   # same size: takes the freed block
+        b.advance(12)
+        for x, y in zip(b.get_state(0), want):
+            assert np.array_equal(x, y)
+        del b
+
+
 def test_checkpoint_resume_and_determinism():
     _require_gpu()
     wl = W.small_wetdry(n=10, N=3)
