@@ -1275,10 +1275,10 @@ step_mfma_kernel(StepArgs a) {
     constexpr bool OPL = !BF && WPB >= 4 && !UPD;
     constexpr int OPS = (S::KSP % 8 == 0) ? S::KSP + 4 : S::KSP;
     static_assert(BF || OPS == mfma_lds_row(N), "LDS image row stride");
-    // four-wave blocks with the early schedule also stage the FP64 reduction
-    // weights (one float4 per thread) after the operator table, so that no
-    // wave loads them from global memory (C4: 607 -> 580 us)
-    constexpr bool WL = OPL && S::EARLY;
+    // blocks that stage the operator table also stage the FP64 reduction
+    // weights (one float4 per thread) after it, so that no wave loads them
+    // from global memory (C4: 607 -> 580 us, C3: 126 -> 120 us per tick)
+    constexpr bool WL = OPL;
     constexpr int WOFF = S::NT * 64 * OPS;   // reduction weights after the operator table
     __shared__ __attribute__((aligned(16))) float sOp[OPL ? WOFF + (WL ? 2 * 64 * S::KR : 0) : 4];
 
@@ -1299,7 +1299,7 @@ step_mfma_kernel(StepArgs a) {
     constexpr int NW4 = 32 * S::KR;   // float4 chunks of the reduction weights
     static_assert(!WL || NW4 <= 64 * WPB, "one chunk of the weights per thread");
     float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (WL) wv = ldg(reinterpret_cast<const float4*>(a.ops.Wred), (unsigned)(tid < NW4 ? tid : 0));
+    if constexpr (WL && S::EARLY) wv = ldg(reinterpret_cast<const float4*>(a.ops.Wred), (unsigned)(tid < NW4 ? tid : 0));
     const int lane = tid & 63, wave = tid >> 6;
     // packed layout: lanes past EPW * LPE are spare; they shadow the wave's
     // last element with the group index LPE (a padding slot everywhere) and
@@ -1447,6 +1447,8 @@ step_mfma_kernel(StepArgs a) {
             const int t = e / (KS * 64), r = e - t * (KS * 64);
             sOp[(t * 64 + (r & 63)) * OPS + (r >> 6)] = ldg(a.ops.Amfma, (unsigned)e);
         }
+        if (tid < NW4)
+            reinterpret_cast<float4*>(sOp)[WOFF / 4 + tid] = ldg(reinterpret_cast<const float4*>(a.ops.Wred), (unsigned)tid);
     }
     if constexpr (OPL) __syncthreads();   // the block's operator table is in LDS
 
@@ -1726,8 +1728,9 @@ step_mfma_kernel(StepArgs a) {
                 red = __builtin_amdgcn_mfma_f64_16x16x4f64(w, bv, red, 0, 0, 0);
             } else {
                 const double bv = (col && nd < Np) ? sVd[ecc][fcc][nd < Np ? nd : 0] : 0.0;
-                red = __builtin_amdgcn_mfma_f64_16x16x4f64(ldg(a.ops.Wred, (unsigned)(s * 64 + lane)), bv, red, 0,
-                                                           0, 0);
+                const double w = WL ? reinterpret_cast<const double*>(sOp + WOFF)[s * 64 + lane]
+                                    : ldg(a.ops.Wred, (unsigned)(s * 64 + lane));
+                red = __builtin_amdgcn_mfma_f64_16x16x4f64(w, bv, red, 0, 0, 0);
             }
         }
         // lane 16 g + c holds row g (0: mean, 1-3: midpoint deviation g-1) of column c
