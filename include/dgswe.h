@@ -113,7 +113,7 @@ typedef struct dg_params {
     int32_t elems_per_block;/* 0 = default for N and path; matrix-core paths: 1, 2, 4 */
                             /* or 8 waves of 64/lanes elements (N = 1, 2, 4: 4, 8,    */
                             /* 16, 32; N = 3: 5, 10, 20, 40; N = 5: 3, 6, 12, 24),    */
-                            /* default 4 waves (8 at N = 5); VALU paths:              */
+                            /* default 8 waves at N = 3, 5, else 4; VALU paths:       */
                             /* floor(256 / Np); anything else is DG_EINVAL            */
     double thin_cut;        /* >= 0; > 0: after the limiters, momentum is set to zero */
                             /* at nodes whose depth is below thin_cut (thin films at  */

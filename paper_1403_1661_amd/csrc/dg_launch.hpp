@@ -192,9 +192,10 @@ int launch_diag_static(const DiagArgs& a, double* out, void* stream);
 int diag_scratch_doubles();
 // elements per block: matrix-core kernel 1, 2, 4 or 8 waves of 64 / lanes
 // elements (N = 1, 2, 4: 4, 8, 16, 32; N = 3: 5, 10, 20, 40; N = 5: 3, 6, 12,
-// 24), default 4 waves (8 at N = 5, the fastest shape there: C4 585 against
-// 551 us); VALU kernel floor(256 / Np) (fixed)
-constexpr int mfma_default_waves(int N) { return N == 5 ? 8 : 4; }
+// 24), default 8 waves at N = 3 and 5 (the fastest shapes there: C5 1035
+// against 966 us, C4 585 against 551 us), 4 waves otherwise; VALU kernel
+// floor(256 / Np) (fixed)
+constexpr int mfma_default_waves(int N) { return N == 3 || N == 5 ? 8 : 4; }
 int step_elems_per_block(int N, int engine);
 
 // Lane groups of the matrix-core kernel.  N = 1, 2, 4: 16 lanes per element
