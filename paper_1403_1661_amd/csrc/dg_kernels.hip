@@ -896,27 +896,6 @@ __device__ __forceinline__ float lane_f32(float x, int byte_addr) {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, x)));
 }
 
-// lane exchange inside rows of 16 lanes by DPP moves (no LDS traffic); CTRL
-// is the DPP control: 0xB1 quad_perm [1,0,3,2] (lane i ^ 1), 0x4E quad_perm
-// [2,3,0,1] (lane i ^ 2), 0x141 row half mirror (lane 7 - i of the 8-lane
-// half), 0x140 row mirror (lane 15 - i)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-// minimum over each row of 16 lanes, in every lane of the row (all lanes
-// of the wave active)
-__device__ __forceinline__ double row_min16(double x) {
-    x = fmin(x, dpp_f64<0xB1>(x));
-    x = fmin(x, dpp_f64<0x4E>(x));    // quad minimum
-    x = fmin(x, dpp_f64<0x141>(x));   // the other quad of the half row
-    return fmin(x, dpp_f64<0x140>(x));   // the other half row
-}
-
 __device__ __forceinline__ void wave_lds_sync() {
     // order this wave's LDS writes before its reads of other lanes' data
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1822,23 +1801,26 @@ step_mfma_kernel(StepArgs a) {
 
 // ---------------------------------------------------------------------------
 // TVB limiter with the positivity modification of Eq. 5.3 (Section 5.3),
-// FP64.  Four lanes per element: lane t < 3 owns edge t (its neighbour t,
-// its stencil row, its characteristic decomposition); the balancing and the
-// P1 output are shared by the quad (lane t writes nodes t, t+4, ...).
+// FP64.  Three lanes per element (21 elements per wave, lane 63 idle): lane
+// t owns edge t (its neighbour t, its stencil row, its characteristic
+// decomposition); the balancing and the P1 output are shared by the three
+// (lane t writes nodes t, t+3, ...).
 // Means and positivity codes come from the step kernel's per-element records,
 // which this kernel only reads, so the order in which elements are limited
 // does not matter.
 // ---------------------------------------------------------------------------
+constexpr int kTvbElems = 84;   // elements per 256-lane block: four waves of 21
+
 __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const int tid = threadIdx.x;
-    const int t = tid & 3;
-    const int lane = tid & 63, qb4 = lane & ~3;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int grp = lane / 3, t = lane - 3 * grp, gb = 3 * grp;   // element of the wave, edge, first lane
     // XCD-contiguous block order, as in the step kernel: the neighbour records
     // a mesh row away are then mostly in the same XCD's L2
-    const int k = a.k_begin + xcd_remap(blockIdx.x, gridDim.x) * 64 + (tid >> 2);
-    if (k >= a.k_end) return;   // the whole quad leaves together
+    const int k = a.k_begin + xcd_remap(blockIdx.x, gridDim.x) * kTvbElems + wave * 21 + grp;
+    if (grp == 21 || k >= a.k_end) return;   // the three lanes of an element leave together
     const unsigned K = (unsigned)a.K;
-    const int ed = t < 3 ? t : 0;   // lane 3 shadows edge 0 and is ignored
+    const int ed = t;
     // round 1: everything indexed by k alone; the element's record holds its
     // post-positivity means and positivity code (the step kernel's snapshot)
     const double2* rec = reinterpret_cast<const double2*>(a.mrec);
@@ -1858,7 +1840,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const float M2 = mp.x;
     const int pairs = __float_as_int(mp.y);
     // round 2: neighbour t's record (means, and its code for the dry test)
-    const int nbt = t == 0 ? cn.x : (t == 1 ? cn.y : (t == 2 ? cn.z : -1));
+    const int nbt = t == 0 ? cn.x : (t == 1 ? cn.y : cn.z);
     bool dry_t = false;
     double nm[3] = {0.0, 0.0, 0.0};
     if (nbt >= 0) {
@@ -1868,13 +1850,13 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         nm[1] = n01.y;
         nm[2] = n23.x;
     }
-    if (((__ballot(dry_t) >> qb4) & 0xFull) != 0) {   // a face neighbour is dry: skipped
+    if (((__ballot(dry_t) >> gb) & 0x7ull) != 0) {   // a face neighbour is dry: skipped
         if (t == 0) a.flags[k] = pp;
         return;
     }
     // mean difference across face t (a wall mirrors the momentum mean)
     double df[3] = {0.0, 0.0, 0.0};
-    if (nbt < 0 && t < 3) {
+    if (nbt < 0) {
         const float* gk = a.geo + 16LL * k;
         const double nx = gk[4 + ed], ny = gk[7 + ed];
         const double mn = qb[1] * nx + qb[2] * ny;
@@ -1890,7 +1872,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     double dbar[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-        dbar[c] = (double)st.x * __shfl(df[c], qb4 + pj) + (double)st.y * __shfl(df[c], qb4 + pk);
+        dbar[c] = (double)st.x * __shfl(df[c], gb + pj) + (double)st.y * __shfl(df[c], gb + pk);
     const double hb = qb[0];
     const double ub = qb[1] / hb, vb = qb[2] / hb;
     const double cc = sqrt(a.g * hb);
@@ -1912,18 +1894,18 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
         mt[r] = small ? a1 : mm;
         all_a1 = all_a1 && (small || a1 == 0.0 || (same && fabs(a1) <= fabs(a2)));
     }
-    if (((__ballot(!all_a1 && t < 3) >> qb4) & 0xFull) == 0) {   // nothing limited: keep P^N
+    if (((__ballot(!all_a1) >> gb) & 0x7ull) == 0) {   // nothing limited: keep P^N
         if (t == 0) a.flags[k] = pp | (1 << 2);
         return;
     }
     double Dl[3];   // increments of edge ed in conserved variables
 #pragma unroll
     for (int q = 0; q < 3; ++q) Dl[q] = Rm[q][0] * mt[0] + Rm[q][1] * mt[1] + Rm[q][2] * mt[2];
-    double D[3][3];   // [field][edge], gathered by every lane of the quad
+    double D[3][3];   // [field][edge], gathered by every lane of the element
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int e = 0; e < 3; ++e) D[q][e] = __shfl(Dl[q], qb4 + e);
+        for (int e = 0; e < 3; ++e) D[q][e] = __shfl(Dl[q], gb + e);
     // balance each conserved component
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -1957,7 +1939,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const LevelArgs L = pick_level(a, level_of(a, k));
     float* Qo = a.Q[1 - L.parity];
     const int Np = a.Np;
-    for (int j = t; j < Np; j += 4) {
+    for (int j = t; j < Np; j += 3) {
         const double p0 = a.phi[j], p1 = a.phi[Np + j], p2 = a.phi[2 * Np + j];
         const long long id = (long long)k * Np + j;
         const double hval = qb[0] + D[0][0] * p0 + D[0][1] * p1 + D[0][2] * p2;
@@ -2189,10 +2171,10 @@ int launch_tvb(const TvbArgs& a, void* stream, void* ev_start, void* ev_stop) {
     if (n <= 0) return 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ev_start)
-        hipExtLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0, s,
+        hipExtLaunchKernelGGL(tvb_kernel, dim3((n + kTvbElems - 1) / kTvbElems), dim3(256), 0, s,
                               static_cast<hipEvent_t>(ev_start), static_cast<hipEvent_t>(ev_stop), 0, a);
     else
-        hipLaunchKernelGGL(tvb_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(tvb_kernel, dim3((n + kTvbElems - 1) / kTvbElems), dim3(256), 0, s, a);
     return check_launch("tvb kernel");
 }
 
