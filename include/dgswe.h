@@ -141,8 +141,8 @@ typedef struct dg_params {
 int32_t dg_default_params(int32_t N, dg_params* p);
 
 /* Validate and set up n_inst instances (n_inst > 1: an ensemble advanced
- * together, each with its own dt): reference element, connectivity,
- * geometry, levels, TVB stencil.  Host only; no device work.
+ * together, each with its own dt; 1 <= n_inst <= 2^23): reference element,
+ * connectivity, geometry, levels, TVB stencil.  Host only; no device work.
  * Errors: DG_EINVAL (null/size), DG_EMESH (see above), DG_ENOMEM. */
 int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p,
                   dg_solver** out);

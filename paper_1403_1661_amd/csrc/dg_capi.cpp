@@ -38,7 +38,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t Q[2], R[3], half, mrec, devs, flags, counters;   // dynamic (checkpointed)
     size_t dyn_begin, dyn_end;
-    size_t B, Blo, dB, geo, conn, stencil;
+    size_t B, Blo, dB, geo, gm, idt, conn, stencil;
     size_t Dr, Ds, LIFT, Amfma, AmfmaL, Abf, Wred, fmask, nodeface, wh, pmid, phi, wfull;
     size_t oIc, oPr, oPs, oP, oLg, oI1, oT1, oT3;
     size_t diag_partial, diag_out;
@@ -80,6 +80,7 @@ struct dg_solver {
     bool bound = false, prepared = false;
     int device = 0;
     // host staging (sorted order, FP32)
+    std::vector<float> gmh, idth;   // staging of the compact metric terms and per-instance time steps
     std::vector<float> geo, stencil, Bh, Qh, dBh;   // dBh: [2][K*Np] bed gradient; Qh: [3][K*Np] (eta hi, hu, hv); Bh, eta relative to the datum
     std::vector<int16_t> Ql;                         // [K*Np] eta lo, 16-bit (see lo_encode)
     std::vector<int16_t> Bl;                         // [K*Np] bed (relative to the datum) lo, 16-bit
@@ -150,6 +151,30 @@ static void shift_bed(dg_solver* h, const Inst& I, double datum) {
             h->Bl[s0 + j] = lo_encode(bh, float(b - double(bh)));
         }
     }
+}
+
+// Geometry records on the device: the 64-byte rows (with each instance's
+// FP32 time step in slot 14), the compact rx, ry, sx, sy array that the
+// matrix-core step kernel reads instead (16 bytes per element), and the
+// per-instance time steps it finds through the connectivity record.  async:
+// on stream s (the host vectors live in the handle until the next call).
+static int upload_geometry(dg_solver* h, hipStream_t s, bool async) {
+    const size_t K = size_t(h->K);
+    for (size_t sidx = 0; sidx < K; ++sidx) h->geo[16 * sidx + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
+    h->gmh.resize(4 * K);
+    for (size_t sidx = 0; sidx < K; ++sidx)
+        for (int c = 0; c < 4; ++c) h->gmh[4 * sidx + c] = h->geo[16 * sidx + c];
+    h->idth.resize(h->inst.size());
+    for (size_t i = 0; i < h->inst.size(); ++i) h->idth[i] = float(h->inst[i].dt_min);
+    const Layout& l = h->lay;
+    const std::pair<size_t, const std::vector<float>*> up[3] = {{l.geo, &h->geo}, {l.gm, &h->gmh}, {l.idt, &h->idth}};
+    for (const auto& u : up) {
+        if (async)
+            HIPCHECK(hipMemcpyAsync(h->ws + u.first, u.second->data(), u.second->size() * 4, hipMemcpyHostToDevice, s));
+        else
+            HIPCHECK(hipMemcpy(h->ws + u.first, u.second->data(), u.second->size() * 4, hipMemcpyHostToDevice));
+    }
+    return DG_OK;
 }
 
 static int engine_of(int precision) {
@@ -347,6 +372,8 @@ static void compute_layout(dg_solver* h) {
     l.Blo = take(KNp * 2);
     l.dB = take(2 * KNp * 4);
     l.geo = take(size_t(h->K) * 64);
+    l.gm = take(size_t(h->K) * 16);
+    l.idt = take(h->inst.size() * 4);
     l.conn = take(size_t(h->K) * 16);
     l.stencil = take(size_t(h->K) * 64);
     const int Np = h->Np, nF = h->nF;
@@ -411,6 +438,7 @@ int32_t dg_default_params(int32_t N, dg_params* p) {
 
 int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p, dg_solver** out) {
     if (!meshes || !p || !out || n_inst < 1) return fail(DG_EINVAL, "null argument or n_inst < 1");
+    if (n_inst > kMaxInstances) return fail(DG_EINVAL, "n_inst must be at most 2^23");
     *out = nullptr;
     if (p->N < 1 || p->N > 6) return fail(DG_EINVAL, "N must be in 1..6");
     if (!(p->thin_cut >= 0)) return fail(DG_EINVAL, "thin_cut must be >= 0");
@@ -509,7 +537,7 @@ int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p
                 packed |= (m.etof[3 * k + f] & 3) << (2 * f);
             }
         }
-        cn[3] = packed;
+        cn[3] = packed | (i << kConnInstShift);
         float* st = &h->stencil[16 * size_t(s)];
         int pairs = 0;
         for (int e = 0; e < 3; ++e) {
@@ -954,6 +982,8 @@ static StepArgs base_step_args(dg_solver* h) {
     for (int s = 0; s < 3; ++s) a.R[s] = reinterpret_cast<float*>(h->ws + l.R[s]);
     a.half = h->L > 1 ? reinterpret_cast<float*>(h->ws + l.half) : nullptr;
     a.geo = reinterpret_cast<const float*>(h->ws + l.geo);
+    a.gm = reinterpret_cast<const float*>(h->ws + l.gm);
+    a.idt = reinterpret_cast<const float*>(h->ws + l.idt);
     a.conn = reinterpret_cast<const int*>(h->ws + l.conn);
     a.mrec = reinterpret_cast<double*>(h->ws + l.mrec);
     a.devs = reinterpret_cast<float*>(h->ws + l.devs);
@@ -1244,7 +1274,6 @@ static int regroup_now(dg_solver* h, hipStream_t s) {
     move_rows(ql, Np, 1, to);
     for (int t = 0; t < 3; ++t) move_rows(S[t], Np, 3, to);
     move_rows(flags, 1, 1, to);
-    for (int sidx = 0; sidx < K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
     // every level: state in buffer 0, ring head 0 (slot 2: R(t - dt), slot 1:
     // R(t - 2 dt), slot 0: R(t - 3 dt), overwritten by the next right-hand side)
     for (int lv = 0; lv < kMaxLevels; ++lv) {
@@ -1258,7 +1287,7 @@ static int regroup_now(dg_solver* h, hipStream_t s) {
     HIPCHECK(hipMemcpy(h->ws + l.R[1], S[1].data(), S[1].size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + l.R[0], S[2].data(), S[2].size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + l.flags, flags.data(), flags.size(), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice));
+    if (const int rc = upload_geometry(h, s, false); rc != DG_OK) return rc;
     HIPCHECK(hipMemcpy(h->ws + l.conn, h->conn.data(), h->conn.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + l.stencil, h->stencil.data(), h->stencil.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice));
@@ -1368,8 +1397,7 @@ int32_t dg_prepare(dg_solver* h, void* stream) {
         I.t_base = 0.0;
         I.tick_base = 0;
     }
-    for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
-    HIPCHECK(hipMemcpyAsync(h->ws + l.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice, s));
+    if (const int rc = upload_geometry(h, s, true); rc != DG_OK) return rc;
     HIPCHECK(hipMemcpyAsync(h->ws + l.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(h->ws + l.Blo, h->Bl.data(), h->Bl.size() * 2, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(h->ws + l.dB, h->dBh.data(), h->dBh.size() * 4, hipMemcpyHostToDevice, s));
@@ -1765,8 +1793,7 @@ int32_t dg_set_checkpoint(dg_solver* h, const void* blob, int64_t bytes, void* s
             h->have_graph = false;
         }
     }
-    for (int sidx = 0; sidx < h->K; ++sidx) h->geo[16 * size_t(sidx) + 14] = float(h->inst[h->inst_of[sidx]].dt_min);
-    HIPCHECK(hipMemcpy(h->ws + h->lay.geo, h->geo.data(), h->geo.size() * 4, hipMemcpyHostToDevice));
+    if (const int rc = upload_geometry(h, s, false); rc != DG_OK) return rc;
     HIPCHECK(hipMemcpy(h->ws + h->lay.B, h->Bh.data(), h->Bh.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + h->lay.Blo, h->Bl.data(), h->Bl.size() * 2, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->ws + h->lay.dyn_begin, b + ckpt_prefix_bytes(h), h->lay.dyn_end - h->lay.dyn_begin,

@@ -1313,8 +1313,7 @@ step_mfma_kernel(StepArgs a) {
     const unsigned idx = (unsigned)kc * Np + (j < Np ? j : Np - 1);
 
     // ---- independent global loads first
-    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * kc);   // rx, ry, sx, sy
-    const float dtmin = ldg(a.geo, 16u * kc + 14u);
+    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.gm), (unsigned)kc);   // rx, ry, sx, sy
     const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
     // buffer views of the block's level arrays (byte offsets < 2^32, checked
     // by the host): resolved on the host for single rate, from the level's
@@ -1349,9 +1348,11 @@ step_mfma_kernel(StepArgs a) {
     const unsigned HB = 4u * (unsigned)a.KnF;   // bytes of one half-trace field
     const BufF32 bH(a.half, 3u * HB);
     float Rn[3];
+    float dtmin;   // the instance's FP32 time step, by the instance id in the connectivity record
     if constexpr (UPD) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) Rn[c] = bR0.ld(idx, c * FB);
+        dtmin = ldg(a.idt, (unsigned)cn.w >> kConnInstShift);
     } else {
     const bool fnode = live && j < nF;
     const int fn = j < nF ? j : 0;
@@ -1418,6 +1419,7 @@ step_mfma_kernel(StepArgs a) {
             hvP = bH.ld(hid, 2u * HB);
         }
     }
+    dtmin = ldg(a.idt, (unsigned)cn.w >> kConnInstShift);
 
     if constexpr (OPL && !S::EARLY) {
         // the operator table in global order (tile, step, lane) to the LDS

@@ -8,6 +8,11 @@
 namespace dgswe {
 
 constexpr int kMaxLevels = 6;
+// Connectivity record (int4 per element): the three neighbours (-1: wall),
+// then the neighbours' face numbers in bits 0-5 (two bits per face) and the
+// element's instance in bits kConnInstShift and up.
+constexpr int kConnInstShift = 8;
+constexpr int kMaxInstances = 1 << (31 - kConnInstShift);
 // Face node fn = f (N+1) + p of the reference triangle (faces s = -1, r + s
 // = 0, r = -1, each in counter-clockwise order) for nodes numbered row by row
 // in s, row j holding N+1-j nodes in increasing r.  The host checks its face
@@ -129,6 +134,8 @@ struct StepArgs {
     unsigned active_bits;  // bit l: level l steps at this tick
     unsigned q_pair_bytes; // byte distance from Q[0] to Q[1]
     const float* geo;      // [K][16]
+    const float* gm;       // [K][4] rx, ry, sx, sy (the geometry row's first four)
+    const float* idt;      // [instances] FP32 time step dt_min of each instance
     const int* conn;       // [K][4]
     double* mrec;          // [K][4] post-positivity means h, hu, hv and the positivity code
     float* devs;           // [9][K] P1 edge-midpoint deviations (elements that are not dry)
