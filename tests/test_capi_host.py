@@ -191,6 +191,18 @@ class _NoStream:
     cuda_stream = 0
 
 
+def test_instance_count_limit(lib):
+    """The connectivity record holds the instance id in 23 bits: dg_create
+    rejects more instances before it reads any mesh."""
+    import ctypes as C
+    one = (dgswe.MeshDesc * 1)()
+    p = dgswe.default_params(2)
+    h = C.c_void_p()
+    assert lib.dg_create(one, 2 ** 23 + 1, C.byref(p), C.byref(h)) == -1
+    assert b"2^23" in lib.dg_last_error()
+    assert not h.value
+
+
 def test_binding_shape_checks():
     """The binding rejects malformed arrays before they reach the library."""
     vx = np.array([0.0, 1.0, 0.0, 1.0])
