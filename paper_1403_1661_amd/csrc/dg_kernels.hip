@@ -25,7 +25,7 @@
 //      deviations) and the positivity limiter of Algorithm 5.2; the element
 //      leaves a record of its FP64 means and positivity code, and its
 //      deviations (stored in FP32) unless it is dry.
-// TVB kernel (four lanes per element, FP64 arithmetic): characteristic minmod
+// TVB kernel (three lanes per element, FP64 arithmetic): characteristic minmod
 // on the edge-midpoint deviations against the neighbours' means, balancing,
 // and the depth rescaling of Eq. 5.3 (Section 5.3).
 #include <hip/hip_ext.h>
@@ -1823,7 +1823,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     if (grp == 21 || k >= a.k_end) return;   // the three lanes of an element leave together
     const unsigned K = (unsigned)a.K;
     const int ed = t;
-    // round 1: everything indexed by k alone; the element's record holds its
+    // first load round: everything indexed by k alone; the element's record holds its
     // post-positivity means and positivity code (the step kernel's snapshot)
     const double2* rec = reinterpret_cast<const double2*>(a.mrec);
     const double2 r01 = ldg(rec, 2u * k), r23 = ldg(rec, 2u * k + 1u);
@@ -1841,7 +1841,7 @@ __global__ void __launch_bounds__(256) tvb_kernel(TvbArgs a) {
     const float2 mp = ldg(reinterpret_cast<const float2*>(a.stencil), 8u * k + 6u);
     const float M2 = mp.x;
     const int pairs = __float_as_int(mp.y);
-    // round 2: neighbour t's record (means, and its code for the dry test)
+    // second load round: neighbour t's record (means, and its code for the dry test)
     const int nbt = t == 0 ? cn.x : (t == 1 ? cn.y : cn.z);
     bool dry_t = false;
     double nm[3] = {0.0, 0.0, 0.0};
