@@ -105,7 +105,7 @@ typedef struct dg_params {
     double tvb_M;           /* TVB constant M (minmod bypass when |a| <= M d_K^2)      */
     double tvb_nu;          /* TVB factor on the neighbour difference (>= 1)          */
     int32_t limiter_mask;   /* DG_LIMIT_* bits                                        */
-    int32_t max_levels;     /* multi-rate levels (1 = single rate AB3), 1..8          */
+    int32_t max_levels;     /* multi-rate levels (1 = single rate AB3), 1..6          */
     int32_t precision;      /* DG_PLAIN_FP32 .. DG_FUSED_BF16X6                        */
     int32_t dry_literal;    /* 1: dry element gets h = h0 (Algorithm 5.2 as printed); */
                             /* 0: h = max(mean, 0), which conserves mass              */
@@ -122,8 +122,9 @@ typedef struct dg_params {
                             /* the nodes); 1: the weak form of Eq. 3.2 with volume    */
                             /* integrals by cubature and face integrals by Gauss      */
                             /* quadrature, both exact to degree 3N (Section 3 and the */
-                            /* Volume/Surface kernels of Section 7): N <= 5, on the   */
-                            /* vector-ALU paths DG_PLAIN_FP32 and DG_FUSED_FP32        */
+                            /* Volume/Surface kernels of Section 7): N <= 5, on        */
+                            /* DG_PLAIN_FP32, DG_FUSED_FP32 (vector ALU) or            */
+                            /* DG_FUSED_MFMA32 (matrix cores); other paths DG_EINVAL   */
     int32_t regroup_every;  /* multi-rate only (max_levels >= 2): 0 = levels fixed    */
                             /* from the mesh (Section 4); >= 3 = levels from every    */
                             /* element's own wave speed (Eq. 4.1 per element, its     */
@@ -141,9 +142,13 @@ typedef struct dg_params {
 int32_t dg_default_params(int32_t N, dg_params* p);
 
 /* Validate and set up n_inst instances (n_inst > 1: an ensemble advanced
- * together, each with its own dt; 1 <= n_inst <= 2^23): reference element,
- * connectivity, geometry, levels, TVB stencil.  Host only; no device work.
- * Errors: DG_EINVAL (null/size), DG_EMESH (see above), DG_ENOMEM. */
+ * together, each with its own dt; 1 <= n_inst <= 2^23): the reference element
+ * on Warp & Blend nodes with Dr, Ds and LIFT, the face connectivity and the
+ * affine geometric factors (Section 3), the multi-rate levels from the element
+ * sizes (Section 4, Eq. 4.1) and the TVB stencil of every edge (Section 5.3).
+ * meshes[n_inst] and p are read during the call only.  Host only; no device
+ * work.  Errors: DG_EINVAL (null/size, parameter out of range), DG_EMESH (see
+ * above), DG_ENOMEM. */
 int32_t dg_create(const dg_mesh_desc* meshes, int32_t n_inst, const dg_params* p,
                   dg_solver** out);
 
@@ -157,7 +162,8 @@ void dg_destroy(dg_solver* h);
 /* Message of the last failed call on this thread ("" if none). */
 const char* dg_last_error(void);
 
-/* Sizes: total elements, Np, Nfp, and the device bytes dg_bind needs. */
+/* Sizes: total elements, Np, Nfp, and the device bytes dg_bind needs (any
+ * pointer may be NULL).  Errors: DG_EINVAL (null handle). */
 int32_t dg_query_sizes(const dg_solver* h, int64_t* total_elements, int32_t* Np,
                        int32_t* Nfp, int64_t* workspace_bytes);
 
@@ -169,10 +175,14 @@ int32_t dg_bind(dg_solver* h, void* device_workspace, int64_t bytes, void* strea
 /* Number of elements of instance `inst`. */
 int32_t dg_instance_elements(const dg_solver* h, int32_t inst, int32_t* K);
 
-/* Physical node coordinates of instance `inst`, [K][Np] each (host). */
+/* Physical node coordinates of instance `inst`, [K][Np] each (host): the
+ * Warp & Blend nodes of the reference triangle mapped affinely onto each
+ * element (Section 3).  Errors: DG_EINVAL. */
 int32_t dg_node_coords(const dg_solver* h, int32_t inst, double* x, double* y);
 
-/* Reference nodes r, s (Np each) and operators, row-major, FP64:
+/* Reference nodes r, s (Np each) and operators of Section 3 (Eq. 3.3; the
+ * over-integrated ones of the weak form, Eq. 3.2, as the Volume and Surface
+ * kernels of Section 7 apply them), row-major, FP64, host arrays:
  * which = 0: Dr (Np x Np), 1: Ds (Np x Np), 2: LIFT (Np x 3Nfp),
  * 3: mass matrix (Np x Np), 4: cell-integral weights w (Np),
  * 5: face node indices (3 x Nfp, as doubles).
@@ -184,7 +194,10 @@ int32_t dg_node_coords(const dg_solver* h, int32_t inst, double* x, double* y);
 int32_t dg_reference(const dg_solver* h, int32_t which, double* out);
 int32_t dg_reference_nodes(const dg_solver* h, double* r, double* s);
 
-/* Bed elevation B at the nodes of instance `inst` ([K][Np], host). */
+/* Bed elevation B at the nodes of instance `inst` ([K][Np], host, FP64): the
+ * bathymetry of the source term of Eq. 2.3 and of the face reconstruction of
+ * Eq. 5.1.  Must come before dg_set_state of the instance.  Errors: DG_EINVAL,
+ * DG_ENUMERIC (non-finite value). */
 int32_t dg_set_bathymetry(dg_solver* h, int32_t inst, const double* B);
 
 /* Initial depth and momenta of instance `inst` ([K][Np] each, host, FP64).
@@ -192,21 +205,30 @@ int32_t dg_set_bathymetry(dg_solver* h, int32_t inst, const double* B);
  * max |u| + sqrt(g h) of this data (Eq. 4.1).  Once every instance has its
  * state (and bathymetry), the first dg_advance applies Q0 = TVB(PP(Q0))
  * (Algorithm 5.1, first line); setting any state resets the time stepping.
- * Errors: DG_ENOTBOUND (no buffer bound), DG_ENUMERIC (non-finite or
- * negative depth), DG_EINVAL. */
+ * Errors: DG_ENOTBOUND (no buffer bound), DG_ESTATE (bathymetry of the
+ * instance not set yet), DG_ENUMERIC (non-finite or negative depth),
+ * DG_EINVAL. */
 int32_t dg_set_state(dg_solver* h, int32_t inst, const double* hh, const double* hu,
                      const double* hv, void* stream);
 
-/* Apply the initial limiting now (otherwise done by the first dg_advance). */
+/* Apply the initial limiting Q0 = TVB(PP(Q0)) of Algorithm 5.1 now, on
+ * `stream` (otherwise done by the first dg_advance); with regrouping, also
+ * the initial levels from the staged state's wave speeds (Section 4, after
+ * Algorithm 4.1).  Errors: DG_ENOTBOUND (no buffer, or an instance without
+ * state or bathymetry), DG_EDEVICE. */
 int32_t dg_prepare(dg_solver* h, void* stream);
 
 /* Enqueue n_steps steps on `stream`: single-rate AB3 steps, or with
- * max_levels > 1 coarse steps of multi-rate AB3 (2^(L-1) ticks of dt_min).
- * Each step: RHS, AB update, positivity limiter, TVB limiter.
- * Errors: DG_ENOTBOUND (state not set), DG_EDEVICE. */
+ * max_levels > 1 coarse steps of multi-rate AB3 (2^(L-1) ticks of dt_min,
+ * Algorithm 4.1).  Each step: the right-hand side of Eq. 3.3 with the flux of
+ * Eq. 5.1-5.2, the Adams-Bashforth update, the positivity limiter of
+ * Algorithm 5.2 and the TVB limiter with Eq. 5.3 (Algorithm 5.1).  Returns
+ * once the work is queued.  Errors: DG_ENOTBOUND (state not set), DG_EINVAL
+ * (n_steps < 0), DG_EDEVICE. */
 int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 
-/* Autotuner (launch shape of the step kernel).  Times the step kernel of
+/* Autotuner (launch shape of the step kernel; the paper tunes the number of
+ * elements per work-group by hand, Section 7.4).  Times the step kernel of
  * the next tick `reps` times for each elements-per-block candidate of the
  * path (matrix-core paths: 1, 2, 4 and 8 waves, see elems_per_block; the VALU
  * paths have one shape) and
@@ -218,27 +240,33 @@ int32_t dg_advance(dg_solver* h, int32_t n_steps, void* stream);
 int32_t dg_autotune(dg_solver* h, int32_t reps, int32_t max_out, int32_t* n_out, int32_t* epb,
                     double* us, void* stream);
 
-/* Current state of instance `inst` as FP64 depth and momenta ([K][Np]).
- * On the device the surface level is an FP32 pair hi + lo (relative to a
- * per-instance datum) and the momenta are FP32.  Synchronises `stream`. */
+/* Current state of instance `inst` as FP64 depth and momenta ([K][Np],
+ * host): the conserved variables h, hu, hv of Eq. 2.1 at the nodes.  On the
+ * device the surface level is an FP32 pair hi + lo (relative to a
+ * per-instance datum) and the momenta are FP32.  Synchronises `stream`.
+ * Errors: DG_EINVAL, DG_ENOTBOUND (no state on the device), DG_EDEVICE. */
 int32_t dg_get_state(dg_solver* h, int32_t inst, double* hh, double* hu, double* hv,
                      void* stream);
 
-/* Face connectivity of instance `inst` in its own element numbering:
- * etoe[K][3] (the element itself for a wall face), etof[K][3]. */
+/* Face connectivity of instance `inst` in its own element numbering
+ * (Section 3: the exterior trace of face f comes from face etof of element
+ * etoe, its nodes in reverse order): etoe[K][3] (the element itself for a wall
+ * face), etof[K][3].  Host only.  Errors: DG_EINVAL. */
 int32_t dg_get_connectivity(const dg_solver* h, int32_t inst, int32_t* etoe, int8_t* etof);
 
 /* Multi-rate level (1 = finest) of every element of instance `inst`, and the
- * instance's dt_min (0 before its state is set); with regrouping, the current
- * levels and step (from dg_prepare on). */
+ * instance's dt_min (0 before its state is set), as Section 4 and Eq. 4.1
+ * assign them; with regrouping, the current levels and step (from dg_prepare
+ * on).  Either pointer may be NULL.  Host only.  Errors: DG_EINVAL. */
 int32_t dg_get_levels(const dg_solver* h, int32_t inst, int8_t* level, double* dt_min);
 
 /* TVB stencil of instance `inst`: pair[K][3][2] face indices used for edge i,
- * alpha[K][3][2] coefficients (Section 5.3). */
+ * alpha[K][3][2] coefficients (Section 5.3).  Host only.  Errors: DG_EINVAL. */
 int32_t dg_get_tvb_stencil(const dg_solver* h, int32_t inst, int8_t* pair, double* alpha);
 
-/* Per-element flag bytes (see DG_PP_* / DG_TVB_*) from the last limiter pass.
- * Synchronises `stream`. */
+/* Per-element flag bytes (see DG_PP_* / DG_TVB_*) from the last limiter pass
+ * (Algorithm 5.2 and Section 5.3), flags[K] in the instance's element order.
+ * Synchronises `stream`.  Errors: DG_EINVAL, DG_ENOTBOUND, DG_EDEVICE. */
 int32_t dg_get_flags(dg_solver* h, int32_t inst, uint8_t* flags, void* stream);
 
 typedef struct dg_diag {
@@ -251,7 +279,10 @@ typedef struct dg_diag {
     int64_t tvb_counts[4];  /* elements per DG_TVB_* code, last limiter pass  */
 } dg_diag;
 
-/* Deterministic FP64 reductions over instance `inst`.  Synchronises `stream`. */
+/* Deterministic FP64 reductions over instance `inst` (the mass that the
+ * positivity limiter conserves, Section 5.2; the minimum depth; the limiter
+ * branch counts), in a fixed order so that repeated calls agree bit for bit.
+ * Synchronises `stream`.  Errors: DG_EINVAL, DG_ENOTBOUND, DG_EDEVICE. */
 int32_t dg_get_diagnostics(dg_solver* h, int32_t inst, dg_diag* d, void* stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
