@@ -377,7 +377,8 @@ def main():
         plain = engines.get("plain_fp32")
 
     # the paper's own discretisation: the over-integrated weak form (cubature
-    # volume term, Gauss surface term; N <= 5) on the vector-ALU kernels
+    # volume term, Gauss surface term; N <= 5): its right-hand side kernel,
+    # then the update and limiters of the matrix-core path
     overint = None
     if not args.no_plain and wl.N <= 5:
         e = make_solver(wl, "fused_mfma32", use_graph=use_graph, tune=False, overint=1)
@@ -391,8 +392,9 @@ def main():
         overint = {"value": per_step * steps / te, "ms_per_step": 1e3 * te / steps,
                    "rhs_kernel_avg_us": rhs_us,
                    "note": "weak form with cubature and Gauss rules exact to degree 3N; RHS kernel "
-                           "with its contractions on the matrix cores, then the vector-ALU update and "
-                           "limiters"}
+                           "with its contractions on the matrix cores, then the AB update, positivity "
+                           "limiter and TVB hand-off in the matrix-core step kernel without its "
+                           "right-hand side, then the TVB kernel"}
         if not args.no_accuracy:
             overint["rel_l2_vs_oracle"] = accuracy_at_configured_steps(e, wl, f"{name}_overint")
         progress(f"over-integrated: {overint['ms_per_step']:.4f} ms/step, RHS kernel {rhs_us:.1f} us")
