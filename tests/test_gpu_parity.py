@@ -279,6 +279,30 @@ def test_ensemble_matches_single_instances(path):
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_ensemble_instance_ids_past_one_byte(path):
+    """300 small instances, each with its own time step: the kernels find an
+    element's time step through the instance id in its connectivity record, so
+    ids above 255 (past the first byte of that field) must reach the right
+    step.  Sampled instances against the oracle, every instance's step against
+    the host's FP64 value."""
+    _require_gpu()
+    wl = W.c5(n_inst=300, kmin=8, kmax=50)
+    log(f"[ensemble300] K={wl.n_elements} path={path}")
+    g = gpu_solver(wl, precision=path)
+    g.advance(20)
+    dts = [g.levels(i)[1] for i in range(300)]
+    assert len(set(dts)) > 50   # the instances really step differently
+    for i in (0, 1, 254, 255, 256, 257, 298, 299):
+        o = oracle_solver(wl, inst=i)
+        assert abs(dts[i] - o.dt_min) <= 1e-12 * o.dt_min
+        o.run(20)
+        err = rel_l2(o, np.stack(g.get_state(i)), o.q)
+        log(f"[ensemble300] inst {i} relL2 {err}")
+        assert err["h"] <= TOL and err["m"] <= TOL
+        assert g.diagnostics(i)["time"] == pytest.approx(20 * o.dt_min, rel=1e-12)
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_bench_config_full_size_first_steps(path):
     """The bench workload (131072 triangles, N=4, wet/dry) at full size in the
     benchmarked launch configuration: 10 steps against the oracle, plus the
