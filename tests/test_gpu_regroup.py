@@ -58,6 +58,45 @@ def test_regroup_parity(path, N):
     assert d["min_depth"] >= 0.0
 
 
+@pytest.mark.parametrize("path", ["fused_fp32", "fused_mfma32"])
+def test_regroup_ensemble(path):
+    """Two graded beaches of different resolution advanced together and
+    regrouped every third coarse step: each instance takes its own levels and
+    time step from its own wave speeds (as the oracle run of that instance
+    alone does), and the re-sorted element order keeps every element's
+    instance, hence its time step."""
+    _require_gpu()
+    a, b = W.graded_beach(n0=2, N=2), W.graded_beach(n0=3, N=2)
+    wl = W.Workload("beach_pair", 2, [a.instances[0], b.instances[0]], steps=12, cfl=a.cfl,
+                    max_levels=a.max_levels)
+    log(f"[regroup-ensemble] K={wl.n_elements} path={path}")
+    g = gpu_solver(wl, precision=path, regroup_every=3)
+    g.prepare()
+    orc = [oracle_solver(wl, inst=i, regroup_every=3) for i in range(2)]
+    lev0 = []
+    for i, o in enumerate(orc):
+        lev, dt = g.levels(i)
+        assert np.array_equal(lev.astype(int), o.levels)
+        assert abs(dt - o.dt_min) <= 1e-12 * o.dt_min
+        lev0.append(lev.copy())
+    assert orc[0].dt_min != orc[1].dt_min
+    g.advance(12)
+    for i, o in enumerate(orc):
+        o.run(12)
+        lev, dt = g.levels(i)
+        assert not np.array_equal(lev, lev0[i])   # the regroups moved elements of every instance
+        flips = int(np.sum(lev.astype(int) != o.levels))
+        err = rel_l2(o, np.stack(g.get_state(i)), o.q)
+        d = g.diagnostics(i)
+        log(f"[regroup-ensemble] inst {i} relL2 h={err['h']:.3e} m={err['m']:.3e} level flips={flips} "
+            f"dt gpu={dt:.9e} oracle={o.dt_min:.9e}")
+        assert flips <= 0.01 * lev.size
+        assert abs(dt - o.dt_min) <= 1e-5 * o.dt_min
+        assert err["h"] <= 1e-5 and err["m"] <= 1e-5, err
+        assert abs(d["time"] - o.t) <= 1e-5 * o.t
+        assert d["min_depth"] >= 0.0
+
+
 def test_regroup_checkpoint_resume():
     """A checkpoint taken after regroups restores onto a fresh solver (whose
     own levels are the initial ones) and continues bit for bit."""
