@@ -967,8 +967,11 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
     constexpr int S1 = overint_mfma_s1(N), T1 = overint_mfma_t1(N), SC = overint_mfma_sc(N);
     constexpr int SG = overint_mfma_sg(N), TN = overint_mfma_tn(N), ST3 = overint_mfma_t3_steps(N);
     constexpr int KC = 4 * SC, KG = 4 * SG;
-    constexpr int X1S = 4 * S1 + 4;                     // row strides padded off the bank period
-    constexpr int XS = (KC > KG ? KC : KG) + 4;
+    // row strides: odd multiples of 4 dwords, so that the 16 rows x 4 k of an
+    // A-operand read, and the four elements' rows of a write, fall in
+    // distinct banks
+    constexpr int X1S = 4 * ((S1 + 1) | 1);
+    constexpr int XS = 4 * (((KC > KG ? KC : KG) / 4 + 1) | 1);
     constexpr int NI = (NGF + 15) / 16;                 // Gauss points per lane
     __shared__ __attribute__((aligned(16))) float sX1[2][16][X1S];
     __shared__ __attribute__((aligned(16))) float sX3[16][XS];
