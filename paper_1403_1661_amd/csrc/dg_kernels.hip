@@ -1168,8 +1168,22 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
     floatx4 acc3[TN];
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) acc3[tn] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the chunk's B operands are loaded before its LDS round trip so that
+    // their latency overlaps it (where they fit in registers: N <= 4)
+    constexpr int SM = SC > SG ? SC : SG;
+    constexpr bool PF = TN * SM <= 16;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
+        const int nst = ch < 3 ? SC : SG;
+        const int off = ch < 3 ? ch * SC : 3 * SC;
+        float bop[PF ? TN : 1][PF ? SM : 1];
+        if constexpr (PF) {
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+                for (int st = 0; st < SM; ++st)
+                    if (st < nst) bop[tn][st] = ldg(a.ops.oT3, (unsigned)(((tn * ST3) + off + st) * 64 + lane));
+        }
         wave_lds_sync();   // the previous chunk's reads (and the flux writes) are done
         if (ch < 3) {
             // rows (e, r): cF1_r, cF2_r or cS_r (cS_h = 0) at cubature node 16 t + c
@@ -1191,16 +1205,15 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
             }
         }
         wave_lds_sync();
-        constexpr int dummy = 0;
-        (void)dummy;
-        const int nst = ch < 3 ? SC : SG;
-        const int off = ch < 3 ? ch * SC : 3 * SC;
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn)
-            for (int st = 0; st < nst; ++st)
-                acc3[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    sX3[ar][4 * st + ak], ldg(a.ops.oT3, (unsigned)(((tn * ST3) + off + st) * 64 + lane)), acc3[tn],
-                    0, 0, 0);
+#pragma unroll
+            for (int st = 0; st < SM; ++st) {
+                if (st >= nst) break;
+                const float bv = PF ? bop[PF ? tn : 0][PF ? st : 0]
+                                    : ldg(a.ops.oT3, (unsigned)(((tn * ST3) + off + st) * 64 + lane));
+                acc3[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(sX3[ar][4 * st + ak], bv, acc3[tn], 0, 0, 0);
+            }
     }
     // ---- lane 16 e + c holds R of element e at node 16 tn + c (rows 4 e .. 4 e + 2)
     if (!live) return;
