@@ -993,6 +993,18 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
     const long long b0 = (long long)kc * Np;
     const float etak = Qs[b0];
     const float lok = lo_decode(etak, Qlo[b0]);
+    // loads that depend on the element alone go out first: the metric terms,
+    // the connectivity and (where they fit in registers) the stage-1 B operands
+    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * (unsigned)kc);   // rx, ry, sx, sy
+    const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
+    constexpr bool PF1 = T1 * S1 <= 8;
+    float b1[PF1 ? T1 : 1][PF1 ? S1 : 1];
+    if constexpr (PF1) {
+#pragma unroll
+        for (int t = 0; t < T1; ++t)
+#pragma unroll
+            for (int st = 0; st < S1; ++st) b1[t][st] = ldg(a.ops.oT1, (unsigned)((t * S1 + st) * 64 + lane));
+    }
     // ---- nodal data into the stage-1 rows and the node table
     for (int j = c; j < 4 * S1; j += 16) {
         float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1029,13 +1041,13 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int st = 0; st < S1; ++st)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sX1[tr][ar][4 * st + ak],
-                                                           ldg(a.ops.oT1, (unsigned)((t * S1 + st) * 64 + lane)),
-                                                           acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    sX1[tr][ar][4 * st + ak],
+                    PF1 ? b1[PF1 ? t : 0][PF1 ? st : 0] : ldg(a.ops.oT1, (unsigned)((t * S1 + st) * 64 + lane)),
+                    acc, 0, 0, 0);
             acc1[tr][t] = acc;
         }
     // ---- stage 2: fluxes and source at this lane's cubature nodes
-    const float4 g0 = ldg(reinterpret_cast<const float4*>(a.geo), 4u * (unsigned)kc);   // rx, ry, sx, sy
     float cf[T1][8];
 #pragma unroll
     for (int t = 0; t < T1; ++t) {
@@ -1056,7 +1068,6 @@ __global__ void __launch_bounds__(64) rhs_overint_mfma_kernel(StepArgs a) {
         cf[t][7] = on ? -g * d * by : 0.f;
     }
     // ---- faces: exterior traces at the own face nodes
-    const int4 cn = ldg(reinterpret_cast<const int4*>(a.conn), (unsigned)kc);
     const float* gk = a.geo + 16LL * kc;
     for (int pn = c; pn < nF; pn += 16) {
         const int f = pn / Nfp, j = pn - f * Nfp;
